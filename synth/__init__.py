@@ -1,0 +1,171 @@
+"""Seeded synthetic inputs shaped like the paper's workloads (input generation only).
+
+The graphs follow the experimental setup of Strausz et al. (Sec. IV-A and
+Table II): R-MAT with a=0.57, b=c=0.19, d=0.05 and EF * 2^scale generated
+pairs, plus uniform (Erdos-Renyi) pairs.  Raw pairs may repeat, be self-loops
+or appear in one direction only; that cleanup belongs to the consumer.
+
+Nothing here computes triangles, degrees or clustering coefficients: both the
+oracle and the GPU path take their inputs from this module and nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "synth.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+RMAT_ABC = (0.57, 0.19, 0.19)
+
+
+def build(force: bool = True) -> str:
+    """Compile the generator library with gcc (OpenMP for the parallel draws)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        i64, u64, f64 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+        p32 = ctypes.POINTER(ctypes.c_int32)
+        lib.synth_rmat.argtypes = [i64, i64, f64, f64, f64, u64, p32, p32]
+        lib.synth_rmat.restype = ctypes.c_int
+        lib.synth_er.argtypes = [i64, i64, u64, p32, p32]
+        lib.synth_er.restype = ctypes.c_int
+        lib.synth_permutation.argtypes = [i64, u64, p32]
+        lib.synth_permutation.restype = None
+        lib.synth_splitmix64_at.argtypes = [u64, u64]
+        lib.synth_splitmix64_at.restype = u64
+        _lib = lib
+    return _lib
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def splitmix64_at(state: int, k: int) -> int:
+    """k-th output of SplitMix64 started from `state` (exposed for its known-answer test)."""
+    return int(_load().synth_splitmix64_at(state & (2**64 - 1), k))
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.int32)
+    _load().synth_permutation(n, seed, _p32(out))
+    return out
+
+
+def rmat(n: int, m_gen: int, seed: int, abc=RMAT_ABC):
+    """R-MAT pairs over [0, n); ceil(log2 n) levels, rejection when n is not a power of two."""
+    src = np.empty(m_gen, dtype=np.int32)
+    dst = np.empty(m_gen, dtype=np.int32)
+    rc = _load().synth_rmat(n, m_gen, abc[0], abc[1], abc[2], seed, _p32(src), _p32(dst))
+    if rc != 0:
+        raise ValueError(f"synth_rmat failed ({rc}) for n={n} m_gen={m_gen}")
+    return src, dst
+
+
+def er(n: int, m_gen: int, seed: int):
+    """m_gen uniform ordered pairs over [0, n)."""
+    src = np.empty(m_gen, dtype=np.int32)
+    dst = np.empty(m_gen, dtype=np.int32)
+    rc = _load().synth_er(n, m_gen, seed, _p32(src), _p32(dst))
+    if rc != 0:
+        raise ValueError(f"synth_er failed ({rc})")
+    return src, dst
+
+
+# ---- the workload recipes -------------------------------------------------------
+
+def er_4096(seed: int = 1):
+    """Uniform random graph, n = 4096, average degree 16: n*16/2 = 32768 raw pairs."""
+    n = 4096
+    s, d = er(n, n * 16 // 2, seed)
+    return n, s, d
+
+
+def rmat_scale(scale: int, edge_factor: int = 16, seed: int = 1):
+    """R-MAT at 2^scale vertices with EF * 2^scale raw pairs (Table II's |E| column)."""
+    n = 1 << scale
+    s, d = rmat(n, edge_factor * n, seed)
+    return n, s, d
+
+
+def batch_specs(count: int = 4096, seed: int = 7):
+    """Specs of the many-small-graphs batch.
+
+    n_i = round(exp(U[ln 64, ln 16384])).  Even i: uniform pairs with average degree
+    U[8, 32] (n_i * deg / 2 raw pairs).  Odd i: R-MAT with edge factor U{8..16}
+    (EF * n_i raw pairs).  Graph i uses generator seed 1000 + i.
+    """
+    st = sub_seed_py(seed)
+    specs = []
+    for i in range(count):
+        u0 = _unit(splitmix64_at(st, 3 * i))
+        u1 = _unit(splitmix64_at(st, 3 * i + 1))
+        n = int(round(math.exp(math.log(64) + u0 * (math.log(16384) - math.log(64)))))
+        if i % 2 == 0:
+            deg = 8.0 + 24.0 * u1
+            specs.append(("er", n, int(round(n * deg / 2)), 1000 + i))
+        else:
+            ef = 8 + int(u1 * 9)
+            specs.append(("rmat", n, ef * n, 1000 + i))
+    return specs
+
+
+def serving_specs(count: int = 64, seed: int = 9, lo_scale: int = 10, hi_scale: int = 21,
+                  edge_factor: int = 16):
+    """Pool of R-MAT graphs with n log-uniform in [2^lo, 2^hi]; graph i uses seed 5000 + i."""
+    st = sub_seed_py(seed)
+    specs = []
+    for i in range(count):
+        u0 = _unit(splitmix64_at(st, i))
+        n = int(round(2.0 ** (lo_scale + u0 * (hi_scale - lo_scale))))
+        specs.append(("rmat", n, edge_factor * n, 5000 + i))
+    return specs
+
+
+def make(spec):
+    """Raw pairs for one spec tuple (kind, n, m_gen, seed) -> (n, src, dst)."""
+    kind, n, m_gen, sd = spec
+    if kind == "er":
+        s, d = er(n, m_gen, sd)
+    else:
+        s, d = rmat(n, m_gen, sd)
+    return n, s, d
+
+
+def poisson_gaps(count: int, rate: float, seed: int = 11) -> np.ndarray:
+    """Exponential inter-arrival gaps (seconds) for a Poisson process of `rate` per second."""
+    st = sub_seed_py(seed)
+    u = np.array([_unit(splitmix64_at(st, k)) for k in range(count)])
+    return -np.log1p(-u) / rate
+
+
+def choices(count: int, bound: int, seed: int) -> np.ndarray:
+    st = sub_seed_py(seed)
+    return np.array([(splitmix64_at(st, k) * bound) >> 64 for k in range(count)], dtype=np.int64)
+
+
+def sub_seed_py(seed: int) -> int:
+    """A stream state for the spec lists (SplitMix64 output 0 of `seed`)."""
+    return splitmix64_at(seed, 0)
+
+
+def _unit(r: int) -> float:
+    return (r >> 11) * (1.0 / (1 << 53))
