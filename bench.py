@@ -1,0 +1,180 @@
+"""Benchmark: per-vertex triangle counts + LCC on one MI355X.
+
+One step = the whole path over one graph whose raw pairs are already in HBM:
+build (loop removal, sort, dedup, degrees, rank, orientation, reverse lists,
+work bins) + count (intersection + scatter) + LCC epilogue, then free.
+Prints one JSON line (see the design doc for the roofline accounting).
+
+    python bench.py [--steps K] [--warmup W] [--workload rmat_s23_ef16]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "edges/sec (TEPS) for TC+LCC, batched vs per-graph, p50/p99 latency"
+
+WORKLOADS = {
+    "rmat_s23_ef16": dict(kind="rmat", scale=23, ef=16, seed=1, offset_bytes=8),
+    "rmat_s20_ef16": dict(kind="rmat", scale=20, ef=16, seed=1, offset_bytes=8),
+    "er_4096_deg16": dict(kind="er", n=4096, seed=1, offset_bytes=4),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_input(w):
+    import synth
+    if w["kind"] == "rmat":
+        return synth.rmat_scale(w["scale"], w["ef"], seed=w["seed"])
+    return synth.er_4096(seed=w["seed"])
+
+
+def count_bytes(info) -> int:
+    """Algorithmic bytes of one count launch (the dominant kernel), from the graph's own counts.
+
+    4 B per candidate probe (one id of a tail of N+(u)), (8 + w) B per kept in-edge
+    (u, tail start, tail length), 4 B per staged entry of N+(v), (4w + 4) B per active
+    vertex (its two offset pairs and its slot in the work list), 8 B per vertex for t.
+    """
+    w = int(info.offset_bytes)
+    return (4 * int(info.wedges) + (8 + w) * int(info.kept_in_edges) + 4 * int(info.staged_entries)
+            + (4 * w + 4) * int(info.active_vertices) + 8 * int(info.n))
+
+
+def stored_traffic(kernel_src: str):
+    """HBM bytes per count launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "count_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(kernel_src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n, s, d, target_s: float):
+    """The oracle's forward algorithm, single-threaded, on a bounded sample of vertices."""
+    import oracle
+    g = oracle.csr(n, s, d)
+    t0 = time.perf_counter()
+    oracle.tc_forward_range(g, 0, 0)  # setup only: orientation of the whole graph
+    setup = time.perf_counter() - t0
+    probe = max(1, n // 2000)
+    t0 = time.perf_counter()
+    _, e1 = oracle.tc_forward_range(g, 0, probe)
+    t1 = time.perf_counter() - t0 - setup
+    frac = min(1.0, max(probe / n, (probe / n) * target_s / max(t1, 1e-3)))
+    hi = max(probe, int(n * frac))
+    t0 = time.perf_counter()
+    _, edges = oracle.tc_forward_range(g, 0, hi)
+    el = time.perf_counter() - t0 - setup
+    return {"value": edges / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"forward algorithm (lowest-ranked vertex owns each triangle) over the "
+                      f"{hi} vertices with ids in [0, {hi}) of {n} (ids are a random permutation, "
+                      f"so a uniform vertex sample); {edges} oriented edges in {el:.1f} s; "
+                      f"orientation setup ({setup:.1f} s) excluded",
+            "seconds": el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat_s23_ef16", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(the path is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2202_13976_amd as pkg
+
+    w = WORKLOADS[args.workload]
+    log(f"[bench] generating {args.workload}")
+    n, s, d = make_input(w)
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(s).to(dev)
+    dst = torch.from_numpy(d).to(dev)
+    tri = torch.empty(n, dtype=torch.int64, device=dev)
+    lcc = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx = pkg.Context(0)
+    ctx.set_profiling(True)
+
+    def step():
+        g = ctx.build_csr(n, src, dst, offset_bytes=w["offset_bytes"])
+        g.run(tri, lcc)
+        tm = g.timings()
+        info = g.info()
+        g.free()
+        return tm, info
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    rec = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rec.append(step())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = rec[-1][1]
+    m = int(info.m)
+    ms_step = el / args.steps * 1e3
+    value = m * args.steps / el
+    phases = {k: float(np.mean([r[0].as_dict()[k] for r in rec])) for k in rec[0][0].as_dict()}
+    count_ms = phases["run_count_ms"]
+    run_ms = phases["run_zero_ms"] + count_ms + phases["run_epilogue_ms"]
+    alg = count_bytes(info)
+    achieved = alg / (count_ms * 1e-3) / 1e9
+    traffic = stored_traffic(os.path.join(ROOT, "paper_2202_13976_amd", "csrc", "count.hip"))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "raw_pairs": int(len(s)), "m_undirected": m,
+                   "offset_bytes": int(info.offset_bytes), "step": "build+count+lcc from raw pairs in HBM",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_count (intersection + scatter)", "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": count_ms},
+        "run_only_teps": m / (run_ms * 1e-3),
+        "phases_ms": phases,
+        "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
+                  "active_vertices": int(info.active_vertices), "block_vertices": int(info.block_vertices),
+                  "staged_entries": int(info.staged_entries), "max_out_degree": int(info.max_out_degree),
+                  "max_degree": int(info.max_degree), "device_bytes": int(info.device_bytes)},
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cb = cpu_baseline(n, s, d, args.cpu_seconds)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

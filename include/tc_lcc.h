@@ -1,0 +1,197 @@
+/*
+ * tc_lcc — per-vertex triangle counts and local clustering coefficients on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Strausz, Vella, Di Girolamo, Besta, Hoefler, "Asynchronous
+ * Distributed-Memory Triangle Counting and LCC with RMA Caching".
+ *   - graph model: simple undirected graph, no multi-edges, no loops (Sec. II-A),
+ *     stored as CSR with sorted adjacency lists (Sec. II-B);
+ *   - t(v): triangles through v, found by intersecting sorted adjacency lists
+ *     with each triangle counted once (Sec. II-C, upper-triangle offset);
+ *   - LCC(v) = 2 t(v) / (d(v) (d(v) - 1)) (Eq. 2); the degree comes for free
+ *     from the offsets (Sec. III-A), so the score follows the count at once;
+ *   - the per-vertex loop of Alg. 3 runs over the whole graph on one GPU.
+ *
+ * Conventions of every call:
+ *   - returns tc_lcc_status; TC_LCC_OK (0) on success.  No C++ exception
+ *     crosses this interface.  On any error no output is written and
+ *     tc_lcc_last_error() holds a message for the calling thread.
+ *   - "device pointer" = memory of the context's GPU (hipMalloc, or a torch
+ *     tensor on that device); "host pointer" = ordinary process memory.
+ *   - hip_stream is a hipStream_t passed as void*; NULL means the default stream.
+ *   - vertex ids are int32 in [0, n); n <= 2^31 - 1.
+ *   - the caller owns every buffer it passes; the library owns contexts,
+ *     graphs and tickets until the matching destroy/free/poll.
+ */
+#ifndef TC_LCC_H
+#define TC_LCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TC_LCC_OK = 0,
+    TC_LCC_INVALID_ARGUMENT = 1, /* null pointer, id outside [0, n), bad size or option */
+    TC_LCC_OUT_OF_MEMORY = 2,    /* a device or host allocation failed */
+    TC_LCC_OVER_BUDGET = 3,      /* the request alone exceeds the context's HBM budget */
+    TC_LCC_NOT_READY = 4,        /* poll: the ticket's work has not finished yet */
+    TC_LCC_BUSY = 5,             /* object still referenced by unfinished work */
+    TC_LCC_DEVICE_ERROR = 6,     /* a HIP call failed */
+    TC_LCC_UNSUPPORTED = 7       /* valid request this build cannot serve */
+} tc_lcc_status;
+
+typedef struct tc_lcc_ctx_s* tc_lcc_ctx;     /* one GPU: memory pool, budget, tuning, queues */
+typedef struct tc_lcc_graph_s* tc_lcc_graph; /* immutable device-resident graph */
+typedef uint64_t tc_lcc_ticket;              /* handle of one submitted batch */
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context may hold at once (graphs + scratch); 0 = no cap.
+ * *out receives the context.  INVALID_ARGUMENT for a bad device or null out. */
+tc_lcc_status tc_lcc_ctx_create(int device, uint64_t hbm_budget_bytes, tc_lcc_ctx* out);
+
+/* Destroy a context.  BUSY while batches are still in flight.  Graphs built in
+ * it must be freed first (BUSY otherwise). */
+tc_lcc_status tc_lcc_ctx_destroy(tc_lcc_ctx ctx);
+
+/* Device bytes the context currently holds (graphs + cached pool blocks). */
+tc_lcc_status tc_lcc_ctx_memory(tc_lcc_ctx ctx, uint64_t* in_use, uint64_t* pooled);
+
+/* ------------------------------------------------------------------ graphs */
+
+/* Build the device graph of n vertices from m_in raw pairs (src[e], dst[e]).
+ *
+ * Pairs may come in any order, repeat, be self-loops, and list an edge in one
+ * or both directions; the graph is the simple undirected graph they describe
+ * (Sec. II-A).  Steps, all on the GPU: drop loops, canonicalise and sort the
+ * pairs, remove repeats, count degrees, rank vertices by (degree, id), relabel
+ * and orient every edge from the lower to the higher rank, build the oriented
+ * CSR with sorted lists (Sec. II-B) and its reverse lists, and record the
+ * degrees used by Eq. 2.
+ *
+ * src, dst: m_in int32 each; device pointers if inputs_on_device != 0, host
+ *   pointers otherwise.  They are only read, and may be freed once this returns
+ *   (the call waits for its stream).
+ * offset_bytes: width of the CSR offsets, 4 or 8, or 0 to pick 4 when the edge
+ *   count fits int32.
+ * Errors: INVALID_ARGUMENT for n outside [1, 2^31-1], m_in < 0 or >= 2^32,
+ *   null pointers with m_in > 0, or any id outside [0, n); OVER_BUDGET if the
+ *   graph would exceed the context budget.  */
+tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
+                               const int32_t* dst, int inputs_on_device, int offset_bytes,
+                               void* hip_stream, tc_lcc_graph* out);
+
+typedef struct {
+    int64_t n;                /* vertices */
+    int64_t m;                /* undirected edges after cleanup */
+    int32_t offset_bytes;     /* 4 or 8 */
+    int32_t max_out_degree;   /* max |N+(v)| of the degree orientation */
+    int64_t max_degree;       /* max d(v) */
+    uint64_t wedges;          /* candidate probes of one count: oriented wedges that can close */
+    uint64_t device_bytes;    /* device memory held by the graph */
+    int64_t kept_in_edges;    /* in-edges (u -> v) with a nonempty tail and nonempty N+(v) */
+    int64_t active_vertices;  /* vertices with at least one probe */
+    int64_t staged_entries;   /* sum of |N+(v)| over active vertices (LDS staging) */
+    int64_t block_vertices;   /* active vertices given a whole block (the rest get one wave) */
+} tc_lcc_graph_stats;
+
+tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);
+
+/* Copy the built structure to host memory (for checking the builder).  Every
+ * pointer may be NULL to skip that array.
+ *   degree[n]     (int64) d(v) of original vertex v
+ *   order[n]      (int32) original id of the vertex of rank r (rank = sort by (d, id))
+ *   out_off[n+1]  (int64) oriented CSR offsets in rank space
+ *   out_adj[m]    (int32) oriented lists: ranks above r, ascending
+ * Synchronous. */
+tc_lcc_status tc_lcc_graph_export(tc_lcc_graph g, int64_t* degree, int32_t* order, int64_t* out_off,
+                                  int32_t* out_adj);
+
+/* Free a graph.  BUSY while a batch that uses it is in flight. */
+tc_lcc_status tc_lcc_graph_free(tc_lcc_graph g);
+
+/* ------------------------------------------------------------------ one graph */
+
+/* Per-vertex triangle counts and LCC of one graph (Alg. 3's loop over every
+ * vertex; Eq. 2).
+ * tri: device pointer, n uint64: tri[v] = t(v), triangles containing vertex v.
+ * lcc: device pointer, n double: 2 t(v) / (d(v) (d(v)-1)) as one IEEE binary64
+ *      division of exact integers; 0.0 when d(v) < 2.  May be NULL to skip.
+ * Asynchronous and ordered on hip_stream; the outputs are complete when the
+ * stream reaches this point.  Runs of one graph are serialised by the library
+ * (they share the graph's scratch counters).  */
+tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, void* hip_stream);
+
+/* ------------------------------------------------------------------ batches */
+
+/* Count many graphs in one persistent launch.  graphs[i] (built in ctx) writes
+ * tri[i] and lcc[i] (device pointers, n_i entries; lcc[i] may be NULL).
+ * Work items over (graph, vertex tile) are taken from a device queue by a grid
+ * sized to the GPU; the launch is recorded once in a HIP graph and replayed.
+ * *out receives a ticket for batch_poll.  Results equal tc_lcc_run's for
+ * every graph.  Graphs and outputs must stay alive until the ticket is done. */
+tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs,
+                                  uint64_t* const* tri, double* const* lcc, tc_lcc_ticket* out);
+
+/* NOT_READY while the batch runs (block == 0), or waits for it (block != 0).
+ * *graphs_done (may be NULL) receives how many graphs of the ticket finished.
+ * OK releases the ticket; INVALID_ARGUMENT for an unknown ticket. */
+tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int* graphs_done);
+
+/* ------------------------------------------------------------------ tuning */
+
+typedef enum {
+    TC_LCC_PROBE_AUTO = 0,   /* hash for large id ranges, bitmap when n is small */
+    TC_LCC_PROBE_HASH = 1,   /* open-addressing hash of N+(v) in LDS */
+    TC_LCC_PROBE_SORTED = 2, /* sorted N+(v) in LDS, binary search (Sec. II-C1) */
+    TC_LCC_PROBE_BITMAP = 3, /* bitmap of N+(v) over [0, n) in LDS with rank counts */
+    TC_LCC_PROBE_MERGE = 4   /* no staging: wave merge-path SSI per edge (Sec. II-C2) */
+} tc_lcc_probe;
+
+typedef struct {
+    int32_t probe;            /* tc_lcc_probe */
+    int32_t group;            /* 0 auto, 1 every vertex to one wave, 2 every vertex to one block */
+    int64_t wave_work_max;    /* vertices with at most this many probes go to one wave */
+    int32_t wave_outdeg_max;  /* ... and at most this |N+(v)| */
+    int32_t block_threads;    /* 256, 512 or 1024 */
+    int32_t merge_ratio_x100; /* MERGE: Eq. 3 cut, 100 * ratio; 0 = log2|B| - 1 */
+    int32_t reserved[7];
+} tc_lcc_tuning;
+
+/* Read or replace the context's tuning.  Results never depend on it. */
+tc_lcc_status tc_lcc_get_tuning(tc_lcc_ctx ctx, tc_lcc_tuning* out);
+tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* in);
+
+/* ------------------------------------------------------------------ profiling */
+
+/* When enabled, tc_lcc_build_csr and tc_lcc_run record HIP events on their stream
+ * around each phase; tc_lcc_graph_timings reads the durations of the graph's last
+ * build and last run (waiting for the run to finish).  Milliseconds. */
+typedef struct {
+    float build_sort_unique_ms; /* canonical keys, radix sort, unique, degrees */
+    float build_rank_ms;        /* rank by (degree, id) */
+    float build_orient_ms;      /* relabel, orient, radix sort, oriented CSR */
+    float build_reverse_ms;     /* reverse lists and per-vertex probe counts */
+    float build_schedule_ms;    /* statistics and degree/work bins */
+    float run_zero_ms;          /* clear counters */
+    float run_count_ms;         /* intersection + scatter kernels */
+    float run_epilogue_ms;      /* LCC epilogue */
+} tc_lcc_timings;
+
+tc_lcc_status tc_lcc_set_profiling(tc_lcc_ctx ctx, int enable);
+tc_lcc_status tc_lcc_graph_timings(tc_lcc_graph g, tc_lcc_timings* out);
+
+/* ------------------------------------------------------------------ misc */
+
+const char* tc_lcc_status_string(tc_lcc_status s);
+const char* tc_lcc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_LCC_H */

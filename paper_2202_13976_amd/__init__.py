@@ -1,0 +1,263 @@
+"""Python binding of the tc_lcc C-ABI (libtc_lcc.so): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module passes
+pointers, sizes and streams.  torch supplies device memory and streams.  If
+the shared library is missing the import of the binding fails loudly: there is
+no fallback path.
+
+Entry points mirror include/tc_lcc.h:
+    Context(device, budget)            tc_lcc_ctx_create / destroy
+    Context.build_csr(n, src, dst)     tc_lcc_build_csr     -> Graph
+    Graph.run(tri, lcc, stream)        tc_lcc_run
+    Context.batch_submit / batch_poll  tc_lcc_batch_submit / poll
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc_lcc.so")
+
+OK, INVALID_ARGUMENT, OUT_OF_MEMORY, OVER_BUDGET, NOT_READY, BUSY, DEVICE_ERROR, UNSUPPORTED = range(8)
+PROBE_AUTO, PROBE_HASH, PROBE_SORTED, PROBE_BITMAP, PROBE_MERGE = range(5)
+
+
+class TcLccError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class GraphStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
+                ("max_out_degree", ctypes.c_int32), ("max_degree", ctypes.c_int64),
+                ("wedges", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("kept_in_edges", ctypes.c_int64), ("active_vertices", ctypes.c_int64),
+                ("staged_entries", ctypes.c_int64), ("block_vertices", ctypes.c_int64)]
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_float) for name in (
+        "build_sort_unique_ms", "build_rank_ms", "build_orient_ms", "build_reverse_ms", "build_schedule_ms",
+        "run_zero_ms", "run_count_ms", "run_epilogue_ms")]
+
+    def as_dict(self):
+        return {name: float(getattr(self, name)) for name, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("probe", ctypes.c_int32), ("group", ctypes.c_int32), ("wave_work_max", ctypes.c_int64),
+                ("wave_outdeg_max", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("merge_ratio_x100", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+_lib = None
+EXPORTS = [
+    "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_build_csr", "tc_lcc_graph_info",
+    "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
+    "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
+    "tc_lcc_status_string", "tc_lcc_last_error",
+]
+
+
+def lib():
+    """Load libtc_lcc.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    st = ctypes.c_int
+    L.tc_lcc_ctx_create.argtypes = [i32, u64, ctypes.POINTER(vp)]
+    L.tc_lcc_ctx_destroy.argtypes = [vp]
+    L.tc_lcc_ctx_memory.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    L.tc_lcc_build_csr.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+    L.tc_lcc_graph_info.argtypes = [vp, ctypes.POINTER(GraphStats)]
+    L.tc_lcc_graph_export.argtypes = [vp, vp, vp, vp, vp]
+    L.tc_lcc_graph_free.argtypes = [vp]
+    L.tc_lcc_run.argtypes = [vp, vp, vp, vp]
+    L.tc_lcc_batch_submit.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(u64)]
+    L.tc_lcc_batch_poll.argtypes = [vp, u64, i32, ctypes.POINTER(i32)]
+    L.tc_lcc_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.tc_lcc_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.tc_lcc_set_profiling.argtypes = [vp, i32]
+    L.tc_lcc_graph_timings.argtypes = [vp, ctypes.POINTER(Timings)]
+    for name in EXPORTS[:-2]:
+        getattr(L, name).restype = st
+    L.tc_lcc_status_string.argtypes = [st]
+    L.tc_lcc_status_string.restype = ctypes.c_char_p
+    L.tc_lcc_last_error.argtypes = []
+    L.tc_lcc_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        detail = lib().tc_lcc_last_error().decode(errors="replace")
+        raise TcLccError(status, where, detail)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Graph:
+    """Immutable device-resident graph (tc_lcc_graph)."""
+
+    def __init__(self, ctx: "Context", handle: ctypes.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self) -> GraphStats:
+        s = GraphStats()
+        _check(lib().tc_lcc_graph_info(self.handle, ctypes.byref(s)), "tc_lcc_graph_info")
+        return s
+
+    @property
+    def n(self) -> int:
+        return int(self.info().n)
+
+    def run(self, tri=None, lcc=None, stream=None, want_lcc: bool = True):
+        """Launch the count + LCC on `stream`; returns (tri, lcc) device tensors (async)."""
+        import torch
+        n = self.n
+        dev = torch.device("cuda", self.ctx.device)
+        if tri is None:
+            tri = torch.empty(n, dtype=torch.int64, device=dev)
+        if lcc is None and want_lcc:
+            lcc = torch.empty(n, dtype=torch.float64, device=dev)
+        assert tri.is_cuda and tri.numel() >= n and tri.element_size() == 8 and tri.is_contiguous()
+        if lcc is not None:
+            assert lcc.is_cuda and lcc.numel() >= n and lcc.dtype == torch.float64 and lcc.is_contiguous()
+        _check(lib().tc_lcc_run(self.handle, _dptr(tri), _dptr(lcc), _stream_ptr(stream)), "tc_lcc_run")
+        return tri, lcc
+
+    def export(self):
+        """(degree[n], order[n], out_off[n+1], out_adj[m]) on the host, for checking the builder."""
+        s = self.info()
+        n, m = int(s.n), int(s.m)
+        deg = np.empty(n, dtype=np.int64)
+        order = np.empty(n, dtype=np.int32)
+        off = np.empty(n + 1, dtype=np.int64)
+        adj = np.empty(max(m, 1), dtype=np.int32)
+        _check(lib().tc_lcc_graph_export(self.handle, deg.ctypes.data, order.ctypes.data, off.ctypes.data,
+                                         adj.ctypes.data), "tc_lcc_graph_export")
+        return deg, order, off, adj[:m]
+
+    def timings(self) -> Timings:
+        t = Timings()
+        _check(lib().tc_lcc_graph_timings(self.handle, ctypes.byref(t)), "tc_lcc_graph_timings")
+        return t
+
+    def free(self):
+        if self.handle:
+            _check(lib().tc_lcc_graph_free(self.handle), "tc_lcc_graph_free")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and lib() is not None:
+                lib().tc_lcc_graph_free(self.handle)
+        except Exception:
+            pass
+
+
+class Context:
+    """One GPU: memory pool with an optional HBM budget, tuning, batch queues (tc_lcc_ctx)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().tc_lcc_ctx_create(device, budget_bytes, ctypes.byref(h)), "tc_lcc_ctx_create")
+        self.handle = h
+
+    def build_csr(self, n: int, src, dst, offset_bytes: int = 0, stream=None) -> Graph:
+        """src/dst: int32 torch CUDA tensors (device path) or numpy arrays (host path)."""
+        import torch
+        if isinstance(src, torch.Tensor):
+            assert src.dtype == torch.int32 and dst.dtype == torch.int32 and src.is_contiguous() and dst.is_contiguous()
+            assert src.numel() == dst.numel()
+            on_dev = 1 if src.is_cuda else 0
+            ps, pd, m = ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.numel()
+            keep = (src, dst)
+        else:
+            s = np.ascontiguousarray(src, dtype=np.int32)
+            d = np.ascontiguousarray(dst, dtype=np.int32)
+            assert s.shape == d.shape
+            on_dev, ps, pd, m = 0, ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(d.ctypes.data), s.size
+            keep = (s, d)
+        h = ctypes.c_void_p()
+        _check(lib().tc_lcc_build_csr(self.handle, n, m, ps, pd, on_dev, offset_bytes, _stream_ptr(stream),
+                                      ctypes.byref(h)), "tc_lcc_build_csr")
+        del keep
+        return Graph(self, h)
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(lib().tc_lcc_get_tuning(self.handle, ctypes.byref(t)), "tc_lcc_get_tuning")
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.tuning()
+        for k, v in kw.items():
+            setattr(t, k, v)
+        _check(lib().tc_lcc_set_tuning(self.handle, ctypes.byref(t)), "tc_lcc_set_tuning")
+        return t
+
+    def set_profiling(self, on: bool = True):
+        _check(lib().tc_lcc_set_profiling(self.handle, 1 if on else 0), "tc_lcc_set_profiling")
+
+    def memory(self):
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().tc_lcc_ctx_memory(self.handle, ctypes.byref(a), ctypes.byref(b)), "tc_lcc_ctx_memory")
+        return int(a.value), int(b.value)
+
+    def batch_submit(self, graphs, tris, lccs=None) -> int:
+        count = len(graphs)
+        gh = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
+        th = (ctypes.c_void_p * count)(*[t.data_ptr() for t in tris])
+        lh = (ctypes.c_void_p * count)(*[(l.data_ptr() if l is not None else 0) for l in (lccs or [None] * count)])
+        tk = ctypes.c_uint64()
+        _check(lib().tc_lcc_batch_submit(self.handle, count, gh, th, lh, ctypes.byref(tk)), "tc_lcc_batch_submit")
+        return int(tk.value)
+
+    def batch_poll(self, ticket: int, block: bool = False):
+        """(done?, graphs_done)."""
+        done = ctypes.c_int()
+        s = lib().tc_lcc_batch_poll(self.handle, ticket, 1 if block else 0, ctypes.byref(done))
+        if s == NOT_READY:
+            return False, int(done.value)
+        _check(s, "tc_lcc_batch_poll")
+        return True, int(done.value)
+
+    def close(self):
+        if self.handle:
+            _check(lib().tc_lcc_ctx_destroy(self.handle), "tc_lcc_ctx_destroy")
+            self.handle = None
+
+
+def tc_lcc(n: int, src, dst, offset_bytes: int = 0, ctx: Context | None = None):
+    """Convenience: build, run, return (tri int64 tensor, lcc float64 tensor) on the device."""
+    own = ctx is None
+    ctx = ctx or Context(0)
+    g = ctx.build_csr(n, src, dst, offset_bytes=offset_bytes)
+    tri, lcc = g.run()
+    import torch
+    torch.cuda.current_stream().synchronize()
+    g.free()
+    if own:
+        ctx.close()
+    return tri, lcc

@@ -1,0 +1,434 @@
+// C-ABI entry points, contexts, graphs and the device memory pool.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace tcl {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+const char* last_error() { return g_err; }
+
+tc_lcc_tuning default_tuning() {
+    tc_lcc_tuning t;
+    memset(&t, 0, sizeof(t));
+    t.probe = TC_LCC_PROBE_AUTO;
+    t.group = 0;
+    t.wave_work_max = 4096;
+    t.wave_outdeg_max = 0;
+    t.block_threads = 256;
+    t.merge_ratio_x100 = 0;
+    return t;
+}
+
+// ------------------------------------------------------------------ pool
+
+size_t Pool::round(size_t bytes) {
+    if (bytes <= 256) return 256;
+    if (bytes <= (1u << 20)) {  // powers of two up to 1 MiB
+        size_t s = 256;
+        while (s < bytes) s <<= 1;
+        return s;
+    }
+    const size_t g = 2u << 20;  // 2 MiB granules above
+    return (bytes + g - 1) / g * g;
+}
+
+tc_lcc_status Pool::alloc(size_t bytes, void** out) {
+    const size_t sz = round(bytes);
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = free_.find(sz);
+    if (it != free_.end()) {
+        void* p = it->second;
+        free_.erase(it);
+        pooled_ -= sz;
+        in_use_ += sz;
+        live_[p] = sz;
+        *out = p;
+        return TC_LCC_OK;
+    }
+    if (budget_ && in_use_ + sz > budget_) {
+        set_error("device budget of %llu bytes exceeded (%llu in use, %zu requested)",
+                  (unsigned long long)budget_, (unsigned long long)in_use_, sz);
+        return TC_LCC_OVER_BUDGET;
+    }
+    if (budget_ && in_use_ + pooled_ + sz > budget_) {
+        // give cached blocks back before asking HIP for more
+        for (auto& kv : free_) {
+            (void)hipFree(kv.second);
+        }
+        free_.clear();
+        pooled_ = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (auto& kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        pooled_ = 0;
+        e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu bytes failed", sz);
+            return TC_LCC_OUT_OF_MEMORY;
+        }
+    }
+    in_use_ += sz;
+    live_[p] = sz;
+    *out = p;
+    return TC_LCC_OK;
+}
+
+void Pool::release(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    const size_t sz = it->second;
+    live_.erase(it);
+    in_use_ -= sz;
+    pooled_ += sz;
+    free_.emplace(sz, p);
+}
+
+void Pool::trim() {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+    pooled_ = 0;
+}
+
+Pool::~Pool() {
+    trim();
+    for (auto& kv : live_) (void)hipFree(kv.first);
+}
+
+}  // namespace tcl
+
+using namespace tcl;
+
+// ------------------------------------------------------------------ misc
+
+extern "C" const char* tc_lcc_status_string(tc_lcc_status s) {
+    switch (s) {
+        case TC_LCC_OK: return "ok";
+        case TC_LCC_INVALID_ARGUMENT: return "invalid argument";
+        case TC_LCC_OUT_OF_MEMORY: return "out of memory";
+        case TC_LCC_OVER_BUDGET: return "over budget";
+        case TC_LCC_NOT_READY: return "not ready";
+        case TC_LCC_BUSY: return "busy";
+        case TC_LCC_DEVICE_ERROR: return "device error";
+        case TC_LCC_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* tc_lcc_last_error(void) { return last_error(); }
+
+// ------------------------------------------------------------------ context
+
+extern "C" tc_lcc_status tc_lcc_ctx_create(int device, uint64_t hbm_budget_bytes, tc_lcc_ctx* out) {
+    if (!out) {
+        set_error("tc_lcc_ctx_create: null out");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        set_error("tc_lcc_ctx_create: device %d not available (%d visible)", device, count);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    TCL_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    TCL_HIP(hipGetDeviceProperties(&prop, device));
+    tc_lcc_ctx c = new (std::nothrow) tc_lcc_ctx_s();
+    if (!c) return TC_LCC_OUT_OF_MEMORY;
+    c->device = device;
+    c->pool.reset(new Pool(device, hbm_budget_bytes));
+    c->tuning = default_tuning();
+    c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    *out = c;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_ctx_destroy(tc_lcc_ctx ctx) {
+    if (!ctx) {
+        set_error("tc_lcc_ctx_destroy: null context");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (ctx->tickets_inflight.load() > 0 || ctx->graphs.load() > 0) {
+        set_error("tc_lcc_ctx_destroy: %d graphs and %d batches still live", ctx->graphs.load(),
+                  ctx->tickets_inflight.load());
+        return TC_LCC_BUSY;
+    }
+    (void)hipSetDevice(ctx->device);
+    batch_engine_destroy(ctx);
+    delete ctx;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_ctx_memory(tc_lcc_ctx ctx, uint64_t* in_use, uint64_t* pooled) {
+    if (!ctx) {
+        set_error("tc_lcc_ctx_memory: null context");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (in_use) *in_use = ctx->pool->in_use();
+    if (pooled) *pooled = ctx->pool->pooled();
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_get_tuning(tc_lcc_ctx ctx, tc_lcc_tuning* out) {
+    if (!ctx || !out) {
+        set_error("tc_lcc_get_tuning: null argument");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = ctx->tuning;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* in) {
+    if (!ctx || !in) {
+        set_error("tc_lcc_set_tuning: null argument");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (in->probe < 0 || in->probe > TC_LCC_PROBE_MERGE || in->group < 0 || in->group > 2 ||
+        in->wave_work_max < 0 || (in->block_threads != 0 && in->block_threads != 256)) {
+        set_error("tc_lcc_set_tuning: value out of range");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuning = *in;
+    ctx->tuning_gen++;
+    return TC_LCC_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+
+static void graph_release(tc_lcc_graph g) {
+    for (void* p : g->blocks) g->ctx->pool->release(p);
+    g->blocks.clear();
+    if (g->last_use) (void)hipEventDestroy(g->last_use);
+    for (hipEvent_t& e : g->d.ev)
+        if (e) (void)hipEventDestroy(e);
+    delete g;
+}
+
+extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
+                                          const int32_t* dst, int inputs_on_device, int offset_bytes,
+                                          void* hip_stream, tc_lcc_graph* out) {
+    if (!ctx || !out) {
+        set_error("tc_lcc_build_csr: null context or out");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (n < 1 || n > 2147483647ll || m_in < 0 || m_in >= (1ll << 32) || (m_in > 0 && (!src || !dst)) ||
+        (offset_bytes != 0 && offset_bytes != 4 && offset_bytes != 8)) {
+        set_error("tc_lcc_build_csr: bad size, pointer or offset width (n=%lld m_in=%lld offset_bytes=%d)",
+                  (long long)n, (long long)m_in, offset_bytes);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    TCL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    tc_lcc_graph g = new (std::nothrow) tc_lcc_graph_s();
+    if (!g) return TC_LCC_OUT_OF_MEMORY;
+    g->ctx = ctx;
+    if (ctx->profiling) {
+        g->d.prof = true;
+        for (hipEvent_t& e : g->d.ev) {
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                graph_release(g);
+                set_error("hipEventCreate failed");
+                return TC_LCC_DEVICE_ERROR;
+            }
+        }
+    }
+    tc_lcc_tuning tn;
+    uint64_t gen;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        tn = ctx->tuning;
+        gen = ctx->tuning_gen;
+    }
+    tc_lcc_status s = build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, st, g);
+    if (s == TC_LCC_OK) {
+        (void)tn;
+        g->d.sched_gen = gen;
+        if (hipEventCreateWithFlags(&g->last_use, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(g->last_use, st) != hipSuccess) {
+            (void)hipGetLastError();
+            s = TC_LCC_DEVICE_ERROR;
+            set_error("hipEventCreate/Record failed");
+        }
+    }
+    if (s != TC_LCC_OK) {
+        (void)hipStreamSynchronize(st);
+        (void)hipGetLastError();
+        graph_release(g);
+        return s;
+    }
+    ctx->graphs++;
+    *out = g;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out) {
+    if (!g || !out) {
+        set_error("tc_lcc_graph_info: null argument");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    out->n = g->d.n;
+    out->m = g->d.m;
+    out->offset_bytes = g->d.off_bytes;
+    out->max_out_degree = g->d.max_dplus;
+    out->max_degree = g->d.max_deg;
+    out->wedges = g->d.wedges;
+    out->device_bytes = g->d.device_bytes;
+    out->kept_in_edges = g->d.m_in_kept;
+    out->active_vertices = g->d.n_block + g->d.n_wave + g->d.n_global;
+    out->staged_entries = (int64_t)g->d.staged;
+    out->block_vertices = g->d.n_block;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_graph_export(tc_lcc_graph g, int64_t* degree, int32_t* order, int64_t* out_off,
+                                             int32_t* out_adj) {
+    if (!g) {
+        set_error("tc_lcc_graph_export: null graph");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    TCL_HIP(hipSetDevice(g->ctx->device));
+    if (g->last_use) TCL_HIP(hipEventSynchronize(g->last_use));
+    const size_t n = (size_t)g->d.n, m = (size_t)g->d.m;
+    std::vector<int32_t> ord(n), dr(n);
+    TCL_HIP(hipMemcpy(ord.data(), g->d.order, n * 4, hipMemcpyDeviceToHost));
+    TCL_HIP(hipMemcpy(dr.data(), g->d.deg_r, n * 4, hipMemcpyDeviceToHost));
+    if (order) memcpy(order, ord.data(), n * 4);
+    if (degree)
+        for (size_t r = 0; r < n; ++r) degree[ord[r]] = dr[r];
+    if (out_off) {
+        if (g->d.off_bytes == 8) {
+            TCL_HIP(hipMemcpy(out_off, g->d.out_off, (n + 1) * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<int32_t> o(n + 1);
+            TCL_HIP(hipMemcpy(o.data(), g->d.out_off, (n + 1) * 4, hipMemcpyDeviceToHost));
+            for (size_t i = 0; i <= n; ++i) out_off[i] = o[i];
+        }
+    }
+    if (out_adj && m) TCL_HIP(hipMemcpy(out_adj, g->d.adj, m * 4, hipMemcpyDeviceToHost));
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_graph_free(tc_lcc_graph g) {
+    if (!g) {
+        set_error("tc_lcc_graph_free: null graph");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (g->inflight.load() > 0) {
+        set_error("tc_lcc_graph_free: graph used by %d unfinished batches", g->inflight.load());
+        return TC_LCC_BUSY;
+    }
+    TCL_HIP(hipSetDevice(g->ctx->device));
+    if (g->last_use) TCL_HIP(hipEventSynchronize(g->last_use));
+    tc_lcc_ctx ctx = g->ctx;
+    graph_release(g);
+    ctx->graphs--;
+    return TC_LCC_OK;
+}
+
+// ------------------------------------------------------------------ one graph
+
+extern "C" tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, void* hip_stream) {
+    if (!g || !tri) {
+        set_error("tc_lcc_run: null graph or output");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    tc_lcc_ctx ctx = g->ctx;
+    TCL_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    tc_lcc_tuning tn;
+    uint64_t gen;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        tn = ctx->tuning;
+        gen = ctx->tuning_gen;
+    }
+    std::lock_guard<std::mutex> lk(g->mu);
+    TCL_HIP(hipStreamWaitEvent(st, g->last_use, 0));
+    if (g->d.sched_gen != gen) {
+        tc_lcc_status s = build_schedule(g, tn, st);
+        if (s != TC_LCC_OK) return s;
+        g->d.sched_gen = gen;
+    }
+    mark(g->d, 6, st);
+    tc_lcc_status s = launch_zero_counts(g, st);
+    mark(g->d, 7, st);
+    if (s == TC_LCC_OK) s = launch_count(g, tn, st);
+    mark(g->d, 8, st);
+    if (s == TC_LCC_OK) s = launch_epilogue(g, tri, lcc, st);
+    mark(g->d, 9, st);
+    if (s != TC_LCC_OK) return s;
+    TCL_HIP(hipEventRecord(g->last_use, st));
+    return TC_LCC_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+extern "C" tc_lcc_status tc_lcc_set_profiling(tc_lcc_ctx ctx, int enable) {
+    if (!ctx) {
+        set_error("tc_lcc_set_profiling: null context");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    ctx->profiling = enable != 0;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_graph_timings(tc_lcc_graph g, tc_lcc_timings* out) {
+    if (!g || !out) {
+        set_error("tc_lcc_graph_timings: null argument");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (!g->d.prof) {
+        set_error("tc_lcc_graph_timings: the graph was built without profiling");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    TCL_HIP(hipSetDevice(g->ctx->device));
+    TCL_HIP(hipEventSynchronize(g->last_use));
+    float ms[10] = {0};
+    auto el = [&](int a, int b) -> float {
+        float x = 0.f;
+        if (hipEventElapsedTime(&x, g->d.ev[a], g->d.ev[b]) != hipSuccess) {
+            (void)hipGetLastError();
+            return -1.f;
+        }
+        return x;
+    };
+    ms[0] = el(0, 1);
+    ms[1] = el(1, 2);
+    ms[2] = el(2, 3);
+    ms[3] = el(3, 4);
+    ms[4] = el(4, 5);
+    ms[5] = el(6, 7);
+    ms[6] = el(7, 8);
+    ms[7] = el(8, 9);
+    out->build_sort_unique_ms = ms[0];
+    out->build_rank_ms = ms[1];
+    out->build_orient_ms = ms[2];
+    out->build_reverse_ms = ms[3];
+    out->build_schedule_ms = ms[4];
+    out->run_zero_ms = ms[5];
+    out->run_count_ms = ms[6];
+    out->run_epilogue_ms = ms[7];
+    return TC_LCC_OK;
+}

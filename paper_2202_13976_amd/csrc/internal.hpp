@@ -1,0 +1,139 @@
+// Internal host-side structures and cross-file launchers of the tc_lcc library.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tc_lcc.h"
+#include "common.hpp"
+
+namespace tcl {
+
+// count kernel geometry: 256-thread blocks (4 waves); one block per heavy vertex,
+// one wave per light vertex, each with an LDS table of N+(v).
+constexpr int kCountThreads = 256;
+constexpr int kWavesPerBlock = kCountThreads / kWave;
+constexpr int32_t kMaxTableSlots = 4096;  // 4096 x (4 B id + 4 B counter) = 32 KiB per block
+
+int resolve_probe(int probe, int64_t n);
+int32_t table_slots(int probe, int32_t dplus_max);
+
+// ------------------------------------------------------------------ device memory pool
+// Caching allocator per context.  Blocks are rounded to size classes and kept on
+// free lists after release; the budget covers blocks in use plus cached blocks.
+class Pool {
+   public:
+    Pool(int device, uint64_t budget) : device_(device), budget_(budget) {}
+    int device() const { return device_; }
+    ~Pool();
+    tc_lcc_status alloc(size_t bytes, void** out);
+    void release(void* p);  // caller guarantees no pending device work uses p
+    void trim();            // hipFree every cached block
+    uint64_t in_use() const { return in_use_; }
+    uint64_t pooled() const { return pooled_; }
+    uint64_t budget() const { return budget_; }
+    static size_t round(size_t bytes);
+
+   private:
+    int device_;
+    uint64_t budget_;
+    uint64_t in_use_ = 0, pooled_ = 0;
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::unordered_map<void*, size_t> live_;
+};
+
+// ------------------------------------------------------------------ graph on the device
+struct GraphDev {
+    int64_t n = 0, m = 0;
+    int off_bytes = 8;   // width of out_off / in_off / in_start
+    int bits = 1;        // ceil(log2 n), at least 1
+    void* out_off = nullptr;    // [n+1] oriented CSR offsets (rank space)
+    int32_t* adj = nullptr;     // [m]   oriented lists, ascending ranks
+    void* in_off = nullptr;     // [n+1] reverse lists: in-edges (u -> v) with a nonempty tail
+    int32_t* in_u = nullptr;    // [m_in_kept] u of each in-edge
+    void* in_start = nullptr;   // [m_in_kept] position in adj right after v inside N+(u)
+    int32_t* in_len = nullptr;  // [m_in_kept] length of that tail of N+(u)
+    int64_t m_in_kept = 0;
+    int32_t* order = nullptr;   // [n] original id of rank r
+    int32_t* deg_r = nullptr;   // [n] degree of rank r
+    int32_t* dplus = nullptr;   // [n] |N+(r)|
+    uint64_t* work = nullptr;   // [n] probes of r's count = sum of its in-edge tails
+    unsigned long long* t_rank = nullptr;  // [n] scratch counters (rank space)
+    unsigned int* counters = nullptr;      // [8] work-queue counters of the count kernel
+    int32_t* vlist = nullptr;   // [n] scheduled vertices: block bin, wave bin, global bin
+    int64_t n_block = 0, n_wave = 0, n_global = 0;
+    int32_t hash_slots = 64;    // LDS hash slots of one block (power of two)
+    int32_t max_dplus = 0;
+    int64_t max_deg = 0;
+    uint64_t wedges = 0;
+    uint64_t staged = 0;        // sum of |N+(v)| over vertices with work
+    uint64_t device_bytes = 0;
+    // profiling events: 0..5 build phase boundaries, 6..9 run phase boundaries
+    hipEvent_t ev[10] = {};
+    bool prof = false;
+    int sched_probe = -1;       // probe the schedule was built for
+    uint64_t sched_gen = ~0ull; // tuning generation the schedule was built for
+};
+
+}  // namespace tcl
+
+struct tc_lcc_ctx_s {
+    int device = 0;
+    std::unique_ptr<tcl::Pool> pool;
+    std::mutex mu;
+    tc_lcc_tuning tuning{};
+    uint64_t tuning_gen = 0;
+    std::atomic<int> graphs{0};
+    std::atomic<int> tickets_inflight{0};
+    int cu_count = 256;
+    size_t lds_per_block = 65536;
+    bool profiling = false;
+    void* batch = nullptr;  // batch engine state (batch.cpp)
+};
+
+struct tc_lcc_graph_s {
+    tc_lcc_ctx ctx = nullptr;
+    tcl::GraphDev d;
+    std::vector<void*> blocks;  // pool blocks owned by the graph
+    hipEvent_t last_use = nullptr;
+    std::atomic<int> inflight{0};
+    std::mutex mu;
+};
+
+namespace tcl {
+
+inline void mark(GraphDev& d, int i, hipStream_t st) {
+    if (d.prof && d.ev[i]) (void)hipEventRecord(d.ev[i], st);
+}
+
+// radix.hip
+size_t radix_sort_scratch_bytes(size_t n);
+hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int nbits, void* scratch,
+                          hipStream_t st, uint64_t** result);
+
+// build.hip
+tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
+                          const int32_t* dst, int inputs_on_device, int offset_bytes,
+                          hipStream_t st, tc_lcc_graph g);
+tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
+
+// count.hip
+tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
+tc_lcc_status launch_epilogue(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st);
+tc_lcc_status launch_zero_counts(tc_lcc_graph g, hipStream_t st);
+
+// batch.hip
+void batch_engine_destroy(tc_lcc_ctx ctx);
+
+// tuning defaults
+tc_lcc_tuning default_tuning();
+
+}  // namespace tcl

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element, bit for bit.
+
+Counts are integers and must match exactly; LCC is one IEEE division of the same
+exact integers on both sides, so it must match bit for bit too (tolerance 0).
+Every case prints its name before it touches the GPU.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2202_13976_amd")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    import gc
+    gc.collect()
+    c.close()
+
+
+def gpu_run(ctx, n, s, d, offset_bytes=0, host=False):
+    if host:
+        g = ctx.build_csr(n, s, d, offset_bytes=offset_bytes)
+    else:
+        g = ctx.build_csr(n, torch.from_numpy(np.ascontiguousarray(s, dtype=np.int32)).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(d, dtype=np.int32)).cuda(),
+                          offset_bytes=offset_bytes)
+    tri, lcc = g.run()
+    torch.cuda.synchronize()
+    out = tri.cpu().numpy().astype(np.uint64), lcc.cpu().numpy()
+    g.free()
+    return out
+
+
+def check(ctx, n, s, d, label, **kw):
+    say(f"[gpu] {label}: n={n} pairs={len(s)} {kw}")
+    t_ref, l_ref = oracle.tc_lcc(n, s, d)
+    t, l = gpu_run(ctx, n, s, d, **kw)
+    bad = np.nonzero(t != t_ref)[0]
+    assert bad.size == 0, f"{label}: {bad.size} counts differ, first at v={bad[:5]}: {t[bad[:5]]} vs {t_ref[bad[:5]]}"
+    assert l.tobytes() == l_ref.tobytes(), f"{label}: LCC bits differ"
+    return t_ref
+
+
+def arr(pairs):
+    if not pairs:
+        return np.zeros(0, np.int32), np.zeros(0, np.int32)
+    a = np.array(pairs, dtype=np.int32)
+    return a[:, 0].copy(), a[:, 1].copy()
+
+
+# ------------------------------------------------------------------ the workloads
+
+def test_er4096_int32(ctx):
+    n, s, d = synth.er_4096(seed=1)
+    check(ctx, n, s, d, "ER n=4096 deg16", offset_bytes=4)
+
+
+@pytest.mark.parametrize("scale", [8, 10, 12, 14, 16])
+@pytest.mark.parametrize("ob", [4, 8])
+def test_rmat_small(ctx, scale, ob):
+    n, s, d = synth.rmat_scale(scale, 16, seed=scale)
+    check(ctx, n, s, d, f"RMAT S{scale}", offset_bytes=ob)
+
+
+def test_rmat_s20_full(ctx):
+    """R-MAT scale 20, edge factor 16, int64 offsets: every vertex against the oracle."""
+    n, s, d = synth.rmat_scale(20, 16, seed=1)
+    check(ctx, n, s, d, "RMAT S20 EF16", offset_bytes=8)
+
+
+def test_rmat_s23_sampled(ctx):
+    """R-MAT scale 23 at full size, as the benchmark runs it: sampled vertices against the
+    oracle one by one (all hubs among them), plus properties that hold at any size."""
+    n, s, d = synth.rmat_scale(23, 16, seed=1)
+    say("[gpu] RMAT S23 EF16 full size")
+    t, l = gpu_run(ctx, n, s, d, offset_bytes=8)
+    g = oracle.csr(n, s, d)
+    deg = g.deg
+    rng = np.random.default_rng(23)
+    sample = np.unique(np.concatenate([rng.choice(n, 400, replace=False), np.argsort(deg)[-12:],
+                                       np.nonzero(deg == 2)[0][:20]]))
+    want = oracle.tc_vertices(g, sample)
+    np.testing.assert_array_equal(t[sample], want)
+    du = deg.astype(np.uint64)
+    assert np.all(t <= du * (du - np.uint64(1)) // np.uint64(2) + (du < 2))
+    assert int(t.sum()) % 3 == 0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ref = np.where(deg >= 2, (2 * t.astype(np.float64)) / (deg.astype(np.float64) * (deg - 1)), 0.0)
+    assert l.tobytes() == ref.tobytes()
+
+
+# ------------------------------------------------------------------ strategies (results never depend on them)
+
+@pytest.mark.parametrize("probe", [pkg.PROBE_HASH, pkg.PROBE_SORTED])
+@pytest.mark.parametrize("group,wave_max", [(0, 4096), (0, 0), (0, 1 << 40), (1, 0), (2, 0)])
+def test_strategies(ctx, probe, group, wave_max):
+    ctx.set_tuning(probe=probe, group=group, wave_work_max=wave_max)
+    try:
+        for label, (n, s, d) in [("RMAT S13", synth.rmat_scale(13, 16, seed=5)),
+                                 ("ER 3000", (3000, *synth.er(3000, 3000 * 20, seed=6)))]:
+            check(ctx, n, s, d, f"{label} probe={probe} group={group} wave_max={wave_max}", offset_bytes=8)
+    finally:
+        ctx.set_tuning(probe=pkg.PROBE_AUTO, group=0, wave_work_max=4096)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_edge_cases(ctx):
+    cases = {
+        "single vertex": (1, [], ),
+        "no edges": (7, []),
+        "only loops": (4, [(0, 0), (1, 1), (3, 3)]),
+        "one triangle, repeated both ways": (3, [(0, 1), (1, 0), (1, 2), (2, 1), (0, 2), (0, 2), (2, 2)]),
+        "star": (60, [(0, i) for i in range(1, 60)]),
+        "wheel": (31, [(0, i) for i in range(1, 31)] + [(i, i % 30 + 1) for i in range(1, 31)]),
+        "K40": (40, list(itertools.combinations(range(40), 2))),
+        "isolated tail": (100000, [(0, 1), (1, 2), (2, 0), (99999, 0), (99999, 1)]),
+    }
+    for label, (n, pairs) in cases.items():
+        s, d = arr(pairs)
+        check(ctx, n, s, d, label)
+
+
+def test_large_clique_global_path(ctx):
+    """K_2200: |N+(v)| reaches 2199, beyond the LDS table, so the global-memory path runs."""
+    n = 2200
+    s, d = arr(list(itertools.combinations(range(n), 2)))
+    check(ctx, n, s, d, "K2200", offset_bytes=8)
+
+
+def test_host_inputs_and_repeats(ctx):
+    n, s, d = synth.rmat_scale(12, 16, seed=77)
+    t_ref = check(ctx, n, s, d, "host inputs", host=True)
+    g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    outs = []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for i in range(4):
+        tri, lcc = g.run(stream=streams[i % 2])
+        outs.append((tri, lcc))
+    torch.cuda.synchronize()
+    for tri, _ in outs:
+        assert np.array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
+    g.free()
+
+
+def test_invalid_inputs(ctx):
+    s = torch.tensor([0, 1, 5], dtype=torch.int32, device="cuda")
+    d = torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda")
+    with pytest.raises(pkg.TcLccError) as e:
+        ctx.build_csr(5, s, d)
+    assert e.value.status == pkg.INVALID_ARGUMENT
+    with pytest.raises(pkg.TcLccError) as e:
+        ctx.build_csr(0, s, d)
+    assert e.value.status == pkg.INVALID_ARGUMENT
+    neg = torch.tensor([-1], dtype=torch.int32, device="cuda")
+    with pytest.raises(pkg.TcLccError):
+        ctx.build_csr(5, neg, neg)
+
+
+def test_builder_structure(ctx):
+    """The exported CSR: degrees, rank order by (degree, id), orientation and sorted lists."""
+    n, s, d = synth.rmat_scale(14, 16, seed=3)
+    g_ref = oracle.csr(n, s, d)
+    say("[gpu] builder structure RMAT S14")
+    g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    deg, order, off, adj = g.export()
+    info = g.info()
+    g.free()
+    np.testing.assert_array_equal(deg, g_ref.deg)
+    assert info.m == g_ref.m and info.n == n
+    want_order = np.lexsort((np.arange(n), g_ref.deg))
+    np.testing.assert_array_equal(order, want_order)
+    src = np.repeat(np.arange(n), np.diff(off))
+    assert np.all(src < adj), "every oriented edge goes to a higher rank"
+    same = src[1:] == src[:-1]
+    assert np.all(adj[1:][same] > adj[:-1][same]), "lists strictly ascending"
+    a, b = order[src], order[adj]
+    got = np.sort(np.minimum(a, b).astype(np.int64) * n + np.maximum(a, b))
+    rows = np.repeat(np.arange(n), g_ref.deg)
+    keep = rows < g_ref.adj
+    want = np.sort(rows[keep].astype(np.int64) * n + g_ref.adj[keep])
+    np.testing.assert_array_equal(got, want)
+    assert info.max_out_degree == int(np.diff(off).max())
