@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--workload", default="rmat_s23_ef16", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy 1 GiB device to device 3 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -166,9 +168,18 @@ def main():
         "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
                   "active_vertices": int(info.active_vertices), "block_vertices": int(info.block_vertices),
                   "staged_entries": int(info.staged_entries), "max_out_degree": int(info.max_out_degree),
-                  "max_degree": int(info.max_degree), "device_bytes": int(info.device_bytes)},
+                  "max_degree": int(info.max_degree), "device_bytes": int(info.device_bytes),
+                  "count_grid": int(info.count_grid), "count_lds_bytes": int(info.count_lds_bytes),
+                  "count_blocks_per_cu": int(info.count_blocks_per_cu), "table_slots": int(info.table_slots)},
     }
     ctx.close()
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 4
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cb = cpu_baseline(n, s, d, args.cpu_seconds)

@@ -97,6 +97,10 @@ typedef struct {
     int64_t active_vertices;  /* vertices with at least one probe */
     int64_t staged_entries;   /* sum of |N+(v)| over active vertices (LDS staging) */
     int64_t block_vertices;   /* active vertices given a whole block (the rest get one wave) */
+    int32_t count_grid;       /* blocks of the last count launch (0 before the first run) */
+    int32_t count_lds_bytes;  /* LDS per block of that launch */
+    int32_t count_blocks_per_cu; /* resident blocks per compute unit the occupancy query allowed */
+    int32_t table_slots;      /* LDS table slots of one block */
 } tc_lcc_graph_stats;
 
 tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);

@@ -36,7 +36,9 @@ class GraphStats(ctypes.Structure):
                 ("max_out_degree", ctypes.c_int32), ("max_degree", ctypes.c_int64),
                 ("wedges", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
                 ("kept_in_edges", ctypes.c_int64), ("active_vertices", ctypes.c_int64),
-                ("staged_entries", ctypes.c_int64), ("block_vertices", ctypes.c_int64)]
+                ("staged_entries", ctypes.c_int64), ("block_vertices", ctypes.c_int64),
+                ("count_grid", ctypes.c_int32), ("count_lds_bytes", ctypes.c_int32),
+                ("count_blocks_per_cu", ctypes.c_int32), ("table_slots", ctypes.c_int32)]
 
 
 class Timings(ctypes.Structure):

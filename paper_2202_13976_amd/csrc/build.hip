@@ -1,11 +1,18 @@
 // Graph builder (CSR with sorted, deduplicated, loop-free lists; Sec. II-A/II-B) and
-// the degree-binned schedule of the count kernels.
+// the degree-binned schedule of the count kernels.  Every step is a stable radix
+// sort, a scan, a gather or a run-boundary pass; no global atomics are used, so
+// hub vertices cause no contention.
 //
-//   raw pairs --(canonical 64-bit keys, loops marked)--> radix sort --> unique + degrees
-//   --> rank vertices by (degree, id) --> relabel + orient every edge low rank -> high rank
-//   --> radix sort --> oriented CSR N+(r) in rank space (lists ascending)
-//   --> reverse lists: for every v, the in-edges (u -> v) whose tail N+(u) after v is nonempty
-//   --> per-vertex probe counts ("work") --> bins for the count kernels.
+//   raw pairs -> canonical 64-bit keys (lo << b | hi, loops marked) -> sort -> unique
+//   degrees   -> lo-side counts from runs of the sorted keys, hi-side counts from runs
+//                after sorting the hi ends (stable sort on bits [32, 32 + b))
+//   rank      -> sort (degree << b | id): rank r = position, order[r] = id
+//   orient    -> keys (min(rank) << b | max(rank)) -> sort -> oriented CSR N+(r) in rank
+//                space with ascending lists; |N+(r)| from runs, offsets by a scan
+//   reverse   -> for each oriented edge i = (u -> v) whose tail N+(u) after v is nonempty
+//                (and N+(v) nonempty): word (v << 32 | i), stable sort on the v bits
+//                -> in-edge lists of v ordered by u; tail start i + 1, tail length
+//                out_off[u + 1] - i - 1; per-vertex probe counts from a scan of lengths.
 //
 // Ranking by (degree, id) orients each edge towards the higher-degree end, so
 // |N+(r)| <= sqrt(2m), and relabelling by rank keeps every list sorted by rank: the
@@ -18,10 +25,13 @@ namespace tcl {
 
 constexpr int kB = 256;
 
+#define GRID_STRIDE(i, n) \
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)(n); i += (size_t)gridDim.x * blockDim.x)
+
 __global__ void k_make_keys(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, size_t m_in,
                             int64_t n, int bits, uint64_t* __restrict__ keys, int* __restrict__ bad) {
     const uint64_t loop = (1ull << (2 * bits)) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m_in; i += (size_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(i, m_in) {
         const int32_t a = src[i], b = dst[i];
         uint64_t key = loop;
         if (a < 0 || a >= n || b < 0 || b >= n) {
@@ -45,29 +55,52 @@ struct UniqueFlag {
     }
 };
 
+// unique keys, and the hi end of each as a word (hi << 32) for the hi-side degree sort
 __global__ void k_compact_unique(const uint64_t* __restrict__ k, size_t n, int bits,
                                  const uint32_t* __restrict__ pos, uint64_t* __restrict__ out,
-                                 int32_t* __restrict__ deg) {
+                                 uint64_t* __restrict__ hi_words) {
     const uint64_t loop = (1ull << (2 * bits)) - 1, mask = (1ull << bits) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(i, n) {
         const uint64_t x = k[i];
         if (x != loop && (i == 0 || k[i - 1] != x)) {
             out[pos[i]] = x;
-            atomicAdd(&deg[x >> bits], 1);
-            atomicAdd(&deg[x & mask], 1);
+            hi_words[pos[i]] = (x & mask) << 32;
         }
     }
 }
 
+// Run boundaries of a sorted array grouped by g(i): first[g] = start, last[g] = one past the
+// end.  Groups that do not occur keep the zeros the caller stored.
+template <typename G>
+__global__ void k_run_bounds(G g, size_t N, uint32_t* __restrict__ first, uint32_t* __restrict__ last) {
+    GRID_STRIDE(i, N) {
+        const uint32_t gi = g(i);
+        if (i == 0 || g(i - 1) != gi) first[gi] = (uint32_t)i;
+        if (i + 1 == N || g(i + 1) != gi) last[gi] = (uint32_t)(i + 1);
+    }
+}
+
+struct GroupShift {
+    const uint64_t* k;
+    int shift;
+    __device__ uint32_t operator()(size_t i) const { return (uint32_t)(k[i] >> shift); }
+};
+
+// deg[v] = (lo-side run length) + (hi-side run length)
+__global__ void k_degrees(const uint32_t* __restrict__ f1, const uint32_t* __restrict__ l1,
+                          const uint32_t* __restrict__ f2, const uint32_t* __restrict__ l2, int64_t n,
+                          int32_t* __restrict__ deg) {
+    GRID_STRIDE(v, n) deg[v] = (int32_t)((l1[v] - f1[v]) + (l2[v] - f2[v]));
+}
+
 __global__ void k_rank_keys(const int32_t* __restrict__ deg, int64_t n, int bits, uint64_t* __restrict__ rk) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        rk[v] = ((uint64_t)(uint32_t)deg[v] << bits) | (uint64_t)v;
+    GRID_STRIDE(v, n) rk[v] = ((uint64_t)(uint32_t)deg[v] << bits) | (uint64_t)v;
 }
 
 __global__ void k_rank_scatter(const uint64_t* __restrict__ rk, int64_t n, int bits, int32_t* __restrict__ order,
                                int32_t* __restrict__ rank, int32_t* __restrict__ deg_r) {
     const uint64_t mask = (1ull << bits) - 1;
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(r, n) {
         const uint64_t x = rk[r];
         const int32_t v = (int32_t)(x & mask);
         order[r] = v;
@@ -77,15 +110,19 @@ __global__ void k_rank_scatter(const uint64_t* __restrict__ rk, int64_t n, int b
 }
 
 __global__ void k_relabel(const uint64_t* __restrict__ uk, size_t m, int bits, const int32_t* __restrict__ rank,
-                          uint64_t* __restrict__ ok, int32_t* __restrict__ dplus) {
+                          uint64_t* __restrict__ ok) {
     const uint64_t mask = (1ull << bits) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(i, m) {
         const uint64_t x = uk[i];
         const uint32_t ra = (uint32_t)rank[x >> bits], rb = (uint32_t)rank[x & mask];
         const uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
         ok[i] = ((uint64_t)lo << bits) | hi;
-        atomicAdd(&dplus[lo], 1);
     }
+}
+
+__global__ void k_run_counts(const uint32_t* __restrict__ f, const uint32_t* __restrict__ l, int64_t n,
+                             int32_t* __restrict__ cnt) {
+    GRID_STRIDE(v, n) cnt[v] = (int32_t)(l[v] - f[v]);
 }
 
 template <typename OffT>
@@ -95,47 +132,67 @@ struct I32In {
     __device__ OffT operator()(size_t i) const { return (int64_t)i < n ? (OffT)p[i] : OffT(0); }
 };
 
+struct LenIn {
+    const int32_t* p;
+    size_t n;
+    __device__ uint64_t operator()(size_t i) const { return i < n ? (uint64_t)(uint32_t)p[i] : 0ull; }
+};
+
 __global__ void k_split_adj(const uint64_t* __restrict__ ok, size_t m, int bits, int32_t* __restrict__ adj) {
     const uint64_t mask = (1ull << bits) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x)
-        adj[i] = (int32_t)(ok[i] & mask);
+    GRID_STRIDE(i, m) adj[i] = (int32_t)(ok[i] & mask);
 }
 
-// in-edge (u -> v) at position i of N+(u): its tail is adj[i+1 .. out_off[u+1]).  Keep it if
-// the tail is nonempty and N+(v) is nonempty (otherwise no triangle can use it).
+// oriented edge i = (u -> v) at position i of N+(u): its tail is adj[i+1 .. out_off[u+1]).
+// Kept (it can close a triangle) if the tail is nonempty and N+(v) is nonempty.
 template <typename OffT>
-__global__ void k_in_count(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
-                           const int32_t* __restrict__ dplus, int32_t* __restrict__ din,
-                           unsigned long long* __restrict__ work) {
+struct KeptFlag {
+    const uint64_t* ok;
+    size_t m;
+    int bits;
+    const OffT* out_off;
+    const int32_t* dplus;
+    __device__ uint32_t operator()(size_t i) const {
+        if (i >= m) return 0;
+        const uint64_t x = ok[i];
+        const uint64_t mask = (1ull << bits) - 1;
+        const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
+        return ((int64_t)out_off[u + 1] - (int64_t)i - 1 > 0 && dplus[v] > 0) ? 1u : 0u;
+    }
+};
+
+template <typename OffT>
+__global__ void k_kept_words(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
+                             const int32_t* __restrict__ dplus, const uint32_t* __restrict__ pos,
+                             uint64_t* __restrict__ words) {
     const uint64_t mask = (1ull << bits) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
+    GRID_STRIDE(i, m) {
         const uint64_t x = ok[i];
         const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
-        const int64_t len = (int64_t)out_off[u + 1] - (int64_t)i - 1;
-        if (len > 0 && dplus[v] > 0) {
-            atomicAdd(&din[v], 1);
-            atomicAdd(&work[v], (unsigned long long)len);
-        }
+        if ((int64_t)out_off[u + 1] - (int64_t)i - 1 > 0 && dplus[v] > 0)
+            words[pos[i]] = ((uint64_t)v << 32) | (uint64_t)i;
     }
 }
 
+// in-edge k (sorted by v, then by position i): u from the oriented key, tail [i+1, out_off[u+1])
 template <typename OffT>
-__global__ void k_in_fill(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
-                          const int32_t* __restrict__ dplus, const OffT* __restrict__ in_off,
-                          int32_t* __restrict__ cursor, int32_t* __restrict__ in_u, OffT* __restrict__ in_start,
-                          int32_t* __restrict__ in_len) {
-    const uint64_t mask = (1ull << bits) - 1;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < m; i += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t x = ok[i];
-        const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
-        const int64_t len = (int64_t)out_off[u + 1] - (int64_t)i - 1;
-        if (len > 0 && dplus[v] > 0) {
-            const OffT p = in_off[v] + (OffT)atomicAdd(&cursor[v], 1);
-            in_u[p] = (int32_t)u;
-            in_start[p] = (OffT)(i + 1);
-            in_len[p] = (int32_t)len;
-        }
+__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const uint64_t* __restrict__ ok,
+                          int bits, const OffT* __restrict__ out_off, int32_t* __restrict__ in_u,
+                          OffT* __restrict__ in_start, int32_t* __restrict__ in_len) {
+    GRID_STRIDE(k, kept) {
+        const uint64_t i = words[k] & 0xffffffffull;
+        const int64_t u = (int64_t)(ok[i] >> bits);
+        in_u[k] = (int32_t)u;
+        in_start[k] = (OffT)(i + 1);
+        in_len[k] = (int32_t)((int64_t)out_off[u + 1] - (int64_t)i - 1);
     }
+}
+
+// work[v] = sum of the tail lengths of v's in-edges = prefix[in_off[v+1]] - prefix[in_off[v]]
+template <typename OffT>
+__global__ void k_work(const OffT* __restrict__ in_off, const uint64_t* __restrict__ prefix, int64_t n,
+                       uint64_t* __restrict__ work) {
+    GRID_STRIDE(v, n) work[v] = prefix[in_off[v + 1]] - prefix[in_off[v]];
 }
 
 // stats[0] = max |N+|, stats[1] = max degree, stats[2] = sum of work (wedges),
@@ -186,7 +243,7 @@ __global__ void k_stats(const int32_t* __restrict__ dplus, const int32_t* __rest
 
 template <typename T>
 __global__ void k_fill(T* p, size_t n, T v) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+    GRID_STRIDE(i, n) p[i] = v;
 }
 
 template <typename T>
@@ -235,6 +292,15 @@ tc_lcc_status keep(tc_lcc_graph g, size_t count, T** out) {
         if (_s != TC_LCC_OK) return _s;      \
     } while (0)
 
+template <typename G>
+hipError_t run_bounds(G g, size_t N, uint32_t* first, uint32_t* last, int64_t n, hipStream_t st) {
+    hipError_t e = fill<uint32_t>(first, (size_t)n, 0u, st);
+    if (e == hipSuccess) e = fill<uint32_t>(last, (size_t)n, 0u, st);
+    if (e != hipSuccess || N == 0) return e;
+    k_run_bounds<G><<<grid_for(N, kB, 16384), kB, 0, st>>>(g, N, first, last);
+    return hipGetLastError();
+}
+
 template <typename OffT>
 tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
                           int on_device, hipStream_t st, tc_lcc_graph g) {
@@ -244,6 +310,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     d.n = n;
     d.bits = bits;
     const size_t M = (size_t)m_in;
+    const size_t N = (size_t)n;
 
     const int32_t* s_dev = src;
     const int32_t* d_dev = dst;
@@ -257,36 +324,43 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         d_dev = b;
     }
 
-    const size_t K = std::max<size_t>({M, (size_t)n, 1});
-    uint64_t *ka, *kb;
+    // three K-word buffers rotate through the sorts; K >= every array they hold (+2 spare words)
+    const size_t K = std::max<size_t>({M, N, 1});
+    uint64_t *ka, *kb, *kc;
     uint32_t* pos;
     void* sort_scratch;
-    TCL_TRY(tmp.get(K, &ka));
-    TCL_TRY(tmp.get(K, &kb));
+    TCL_TRY(tmp.get(K + 1, &ka));
+    TCL_TRY(tmp.get(K + 1, &kb));
+    TCL_TRY(tmp.get(K + 1, &kc));
     TCL_TRY(tmp.get(M + 1, &pos));
-    TCL_TRY(tmp.get(radix_sort_scratch_bytes(K) + sizeof(uint32_t) * scan_scratch_elems(K + 1) * 2 + 1024,
-                    (uint8_t**)&sort_scratch));
+    const size_t rs_bytes = radix_sort_scratch_bytes(K);
+    TCL_TRY(tmp.get(rs_bytes + sizeof(uint64_t) * scan_scratch_elems(K + 1) + 1024, (uint8_t**)&sort_scratch));
+    uint32_t* scan32 = (uint32_t*)((uint8_t*)sort_scratch + rs_bytes);
+    OffT* scanO = (OffT*)scan32;
+    uint64_t* scan64 = (uint64_t*)scan32;
     int* bad;
     TCL_TRY(tmp.get(16, &bad));
     TCL_HIP(fill<int>(bad, 16, 0, st));
-
+    uint32_t *f1, *l1, *f2, *l2;
+    TCL_TRY(tmp.get(N, &f1));
+    TCL_TRY(tmp.get(N, &l1));
+    TCL_TRY(tmp.get(N, &f2));
+    TCL_TRY(tmp.get(N, &l2));
     int32_t* deg;
-    TCL_TRY(tmp.get((size_t)n, &deg));
-    TCL_HIP(fill<int32_t>(deg, (size_t)n, 0, st));
+    TCL_TRY(tmp.get(N, &deg));
 
     mark(d, 0, st);
-    // 1. canonical keys, sort, unique, degrees
+    // 1. canonical keys, sort, unique
     uint64_t* sorted = ka;
     uint64_t* ukeys = kb;
     uint32_t m32 = 0;
     if (M > 0) {
         k_make_keys<<<grid_for(M, kB, 8192), kB, 0, st>>>(s_dev, d_dev, M, n, bits, ka, bad);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(ka, kb, M, 2 * bits, sort_scratch, st, &sorted));
+        TCL_HIP(radix_sort_u64(ka, kb, M, 0, 2 * bits, sort_scratch, st, &sorted));
         ukeys = (sorted == ka) ? kb : ka;
-        uint32_t* sscr = (uint32_t*)((uint8_t*)sort_scratch + radix_sort_scratch_bytes(K));
-        TCL_HIP(exclusive_scan<uint32_t>(UniqueFlag{sorted, M, (1ull << (2 * bits)) - 1}, M + 1, pos, sscr, st));
-        k_compact_unique<<<grid_for(M, kB, 8192), kB, 0, st>>>(sorted, M, bits, pos, ukeys, deg);
+        TCL_HIP(exclusive_scan<uint32_t>(UniqueFlag{sorted, M, (1ull << (2 * bits)) - 1}, M + 1, pos, scan32, st));
+        k_compact_unique<<<grid_for(M, kB, 8192), kB, 0, st>>>(sorted, M, bits, pos, ukeys, kc);
         TCL_HIP(hipGetLastError());
         int hb = 0;
         TCL_HIP(hipMemcpyAsync(&m32, pos + M, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -303,66 +377,70 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         set_error("tc_lcc_build_csr: %zu edges do not fit 4-byte offsets", m);
         return TC_LCC_INVALID_ARGUMENT;
     }
+    uint64_t* spare = (ukeys == ka) ? kb : ka;  // held the raw sorted keys, free from here on
+    // degrees: lo ends are runs of the (lo, hi)-sorted unique keys; hi ends are runs after a
+    // stable sort of the words (hi << 32) on their high bits
+    TCL_HIP(run_bounds(GroupShift{ukeys, bits}, m, f1, l1, n, st));
+    {
+        uint64_t* hs = kc;
+        if (m > 0) TCL_HIP(radix_sort_u64(kc, spare, m, 32, bits, sort_scratch, st, &hs));
+        TCL_HIP(run_bounds(GroupShift{hs, 32}, m, f2, l2, n, st));
+    }
+    k_degrees<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, f2, l2, n, deg);
+    TCL_HIP(hipGetLastError());
 
     mark(d, 1, st);
     // 2. rank by (degree, id)
     int32_t* rank;
-    TCL_TRY(tmp.get((size_t)n, &rank));
-    TCL_TRY(keep(g, (size_t)n, &d.order));
-    TCL_TRY(keep(g, (size_t)n, &d.deg_r));
+    TCL_TRY(tmp.get(N, &rank));
+    TCL_TRY(keep(g, N, &d.order));
+    TCL_TRY(keep(g, N, &d.deg_r));
     {
-        uint64_t *rk, *rk2, *rs;
-        TCL_TRY(tmp.get((size_t)n, &rk));
-        TCL_TRY(tmp.get((size_t)n, &rk2));
-        k_rank_keys<<<grid_for(n, kB, 8192), kB, 0, st>>>(deg, n, bits, rk);
+        uint64_t* rs = spare;
+        k_rank_keys<<<grid_for(N, kB, 8192), kB, 0, st>>>(deg, n, bits, spare);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(rk, rk2, (size_t)n, 2 * bits, sort_scratch, st, &rs));
-        k_rank_scatter<<<grid_for(n, kB, 8192), kB, 0, st>>>(rs, n, bits, d.order, rank, d.deg_r);
+        TCL_HIP(radix_sort_u64(spare, kc, N, 0, 2 * bits, sort_scratch, st, &rs));
+        k_rank_scatter<<<grid_for(N, kB, 8192), kB, 0, st>>>(rs, n, bits, d.order, rank, d.deg_r);
         TCL_HIP(hipGetLastError());
     }
 
     mark(d, 2, st);
     // 3. relabel + orient, sort, oriented CSR
-    TCL_TRY(keep(g, (size_t)n, &d.dplus));
-    TCL_HIP(fill<int32_t>(d.dplus, (size_t)n, 0, st));
-    uint64_t* okeys = sorted;  // reuse the buffer that held the raw sorted keys
+    uint64_t* okeys = spare;
     uint64_t* osorted = okeys;
+    TCL_TRY(keep(g, N, &d.dplus));
     OffT* out_off;
-    TCL_TRY(keep(g, (size_t)n + 1, &out_off));
+    TCL_TRY(keep(g, N + 1, &out_off));
     d.out_off = out_off;
     TCL_TRY(keep(g, std::max<size_t>(m, 1), &d.adj));
-    uint32_t* sscr = (uint32_t*)((uint8_t*)sort_scratch + radix_sort_scratch_bytes(K));
-    OffT* scan_scr = (OffT*)sscr;
     if (m > 0) {
-        k_relabel<<<grid_for(m, kB, 8192), kB, 0, st>>>(ukeys, m, bits, rank, okeys, d.dplus);
+        k_relabel<<<grid_for(m, kB, 8192), kB, 0, st>>>(ukeys, m, bits, rank, okeys);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(okeys, ukeys, m, 2 * bits, sort_scratch, st, &osorted));
+        TCL_HIP(radix_sort_u64(okeys, kc, m, 0, 2 * bits, sort_scratch, st, &osorted));
     }
-    TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{d.dplus, n}, (size_t)n + 1, out_off, scan_scr, st));
+    TCL_HIP(run_bounds(GroupShift{osorted, bits}, m, f1, l1, n, st));
+    k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, n, d.dplus);
+    TCL_HIP(hipGetLastError());
+    TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{d.dplus, n}, N + 1, out_off, scanO, st));
     if (m > 0) {
         k_split_adj<<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, d.adj);
         TCL_HIP(hipGetLastError());
     }
 
     mark(d, 3, st);
-    // 4. reverse lists with nonempty tails, and per-vertex work
-    int32_t* din;
-    TCL_TRY(tmp.get((size_t)n, &din));
-    TCL_HIP(fill<int32_t>(din, (size_t)n, 0, st));
-    TCL_TRY(keep(g, (size_t)n, &d.work));
-    TCL_HIP(fill<uint64_t>(d.work, (size_t)n, 0, st));
+    // 4. reverse lists (in-edges with a nonempty tail), sorted by v then by position (so by u)
+    uint64_t* wa = nullptr;
+    uint64_t* wb = nullptr;
+    for (uint64_t* b : {ka, kb, kc})
+        if (b != osorted) (wa ? wb : wa) = b;
+    uint32_t kept = 0;
     if (m > 0) {
-        k_in_count<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, din,
-                                                               (unsigned long long*)d.work);
+        TCL_HIP(exclusive_scan<uint32_t>(KeptFlag<OffT>{osorted, m, bits, out_off, d.dplus}, m + 1, pos, scan32, st));
+        k_kept_words<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, pos, wa);
         TCL_HIP(hipGetLastError());
+        TCL_HIP(hipMemcpyAsync(&kept, pos + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipStreamSynchronize(st));
     }
-    OffT* in_off;
-    TCL_TRY(keep(g, (size_t)n + 1, &in_off));
-    d.in_off = in_off;
-    TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{din, n}, (size_t)n + 1, in_off, scan_scr, st));
-    OffT kept = 0;
-    TCL_HIP(hipMemcpyAsync(&kept, in_off + n, sizeof(OffT), hipMemcpyDeviceToHost, st));
-    TCL_HIP(hipStreamSynchronize(st));
     d.m_in_kept = (int64_t)kept;
     const size_t KE = std::max<size_t>((size_t)kept, 1);
     TCL_TRY(keep(g, KE, &d.in_u));
@@ -370,22 +448,36 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_TRY(keep(g, KE, &in_start));
     d.in_start = in_start;
     TCL_TRY(keep(g, KE, &d.in_len));
-    if (m > 0) {
-        TCL_HIP(fill<int32_t>(din, (size_t)n, 0, st));
-        k_in_fill<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, in_off, din,
-                                                              d.in_u, in_start, d.in_len);
+    OffT* in_off;
+    TCL_TRY(keep(g, N + 1, &in_off));
+    d.in_off = in_off;
+    TCL_TRY(keep(g, N, &d.work));
+    uint64_t* ws = wa;
+    if (kept > 0) TCL_HIP(radix_sort_u64(wa, wb, kept, 32, bits, sort_scratch, st, &ws));
+    TCL_HIP(run_bounds(GroupShift{ws, 32}, kept, f2, l2, n, st));
+    int32_t* din = deg;  // degrees by vertex are not needed any more (deg_r keeps them by rank)
+    k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f2, l2, n, din);
+    TCL_HIP(hipGetLastError());
+    TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{din, n}, N + 1, in_off, scanO, st));
+    if (kept > 0) {
+        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, osorted, bits, out_off, d.in_u,
+                                                                 in_start, d.in_len);
         TCL_HIP(hipGetLastError());
     }
+    uint64_t* prefix = (ws == wa) ? wb : wa;  // kept + 1 prefix sums of the tail lengths
+    TCL_HIP(exclusive_scan<uint64_t>(LenIn{d.in_len, (size_t)kept}, (size_t)kept + 1, prefix, scan64, st));
+    k_work<OffT><<<grid_for(N, kB, 8192), kB, 0, st>>>(in_off, prefix, n, d.work);
+    TCL_HIP(hipGetLastError());
 
     mark(d, 4, st);
     // 5. run scratch and statistics
-    TCL_TRY(keep(g, (size_t)n, &d.t_rank));
+    TCL_TRY(keep(g, N, &d.t_rank));
     TCL_TRY(keep(g, 64, &d.counters));
-    TCL_TRY(keep(g, (size_t)n, &d.vlist));
+    TCL_TRY(keep(g, N, &d.vlist));
     unsigned long long* stats;
     TCL_TRY(tmp.get(4, &stats));
     TCL_HIP(fill<unsigned long long>(stats, 4, 0ull, st));
-    k_stats<<<grid_for(n, kB, 2048), kB, 0, st>>>(d.dplus, d.deg_r, (const unsigned long long*)d.work, n, stats);
+    k_stats<<<grid_for(N, kB, 2048), kB, 0, st>>>(d.dplus, d.deg_r, (const unsigned long long*)d.work, n, stats);
     TCL_HIP(hipGetLastError());
     unsigned long long hs[4] = {0, 0, 0, 0};
     TCL_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
@@ -455,7 +547,8 @@ __global__ void k_vlist(const uint64_t* __restrict__ keys, int64_t cnt, int bits
 // LDS slots of one block's table: hash tables get twice the list length (load <= 1/2).
 int32_t table_slots(int probe, int32_t dplus_max) {
     int32_t need = probe == TC_LCC_PROBE_SORTED ? dplus_max : 2 * dplus_max;
-    int32_t s = 256;
+    // every wave's slice of the table holds at least the 64 slots of the smallest hash table
+    int32_t s = 64 * kWavesPerBlock;
     while (s < need && s < kMaxTableSlots) s <<= 1;
     return s;
 }
@@ -481,7 +574,7 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     k_classify<<<grid_for(n, kB, 4096), kB, 0, st>>>((const unsigned long long*)d.work, d.dplus, d.n, d.bits,
                                                      tn.wave_work_max, wave_cap, block_cap, group, ka, counts);
     TCL_HIP(hipGetLastError());
-    TCL_HIP(radix_sort_u64(ka, kb, n, d.bits + 6, scr, st, &res));
+    TCL_HIP(radix_sort_u64(ka, kb, n, 0, d.bits + 6, scr, st, &res));
     unsigned long long hc[64];
     TCL_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st));
     TCL_HIP(hipStreamSynchronize(st));

@@ -4,24 +4,27 @@
 // found exactly once, at its middle vertex v: for every in-edge (u -> v), the tail
 // of N+(u) after v holds the candidates w > v (rank-space form of the
 // upper-triangle offset of Sec. II-C), and each candidate is probed against N+(v),
-// which is staged once per v in LDS.  So one candidate probe is one oriented wedge
-// (u; v, w), and the total work is the number of oriented wedges, sum_u C(|N+(u)|, 2).
+// which is staged once per v in LDS.  One candidate probe is one oriented wedge
+// (u; v, w), so the work is the number of oriented wedges, sum_u C(|N+(u)|, 2).
 //
 // Scatter (each triangle adds 1 to t(u), t(v), t(w); Alg. 3 accumulates t):
 //   t(v): summed in registers, one atomic per wave and vertex;
 //   t(u): one LDS counter per in-edge, one global atomic per in-edge that closed any;
 //   t(w): one LDS counter per entry of N+(v), one global atomic per entry that hit.
-// So the number of global atomics is at most 2m + n whatever the triangle count.
+// So there are at most 2m + n global atomics whatever the triangle count.
 //
 // Load balance: a persistent grid pulls vertices from device queues.  Heavy
-// vertices (by probe count, heaviest first) take a whole 256-thread block; light
-// ones take one wave with a quarter of the block's LDS table.  Inside a group,
-// each wave takes 64 in-edges at a time and flattens their tails so that the 64
-// lanes read consecutive candidates (coalesced), mapping a flat index back to its
-// in-edge by a 6-step binary search over the wave's prefix sums in LDS.
+// vertices (by probe count, heaviest first) take a whole block; light ones take
+// one wave with a slice of the block's LDS.  Each wave takes 64 in-edges at a
+// time and walks their tails one after the other in windows of 64 candidates
+// (lane i reads candidate base + i: coalesced), with all loop bounds wave-uniform
+// (scalar).  A ring of kUnroll windows is prefetched, so that many loads stay in
+// flight across tail boundaries.  Hits per tail are popcounts of ballots.
 #include "internal.hpp"
 
 namespace tcl {
+
+constexpr int kUnroll = 4;  // prefetched windows of 64 candidates
 
 template <typename OffT>
 struct CountArgs {
@@ -35,20 +38,11 @@ struct CountArgs {
     int64_t n_block, n_wave, n_global;
     unsigned long long* t;
     unsigned int* ctr;
-    int32_t slots;  // table slots of a block (power of two)
+    int32_t slots;  // table slots of a block (power of two, >= 256)
 };
 
-// per-wave LDS: prefix P[64], per-in-edge hit counters E[64], tail starts S[64]
-template <typename OffT>
-struct WaveMeta {
-    uint32_t P[kWave];
-    uint32_t E[kWave];
-    OffT S[kWave];
-};
-
-__device__ __forceinline__ uint32_t hash_slot(int32_t x, int logT) {
-    return ((uint32_t)x * 0x9E3779B1u) >> (32 - logT);
-}
+// bucket hash: high bits of a 24x24-bit product (one full-rate multiply)
+__device__ __forceinline__ uint32_t hash32(int32_t x) { return __umul24((uint32_t)x, 0x9E3779u); }
 
 template <int NWAVES>
 __device__ __forceinline__ void group_sync() {
@@ -56,10 +50,68 @@ __device__ __forceinline__ void group_sync() {
     else wave_lds_sync();
 }
 
-// One vertex v, processed by a group of NWAVES waves (gtid/gsize = thread index/size in the group).
+// Bucketed open addressing: 4 slots per bucket read with one 16-byte LDS load; a key
+// lives in the first bucket with room from its hash bucket on.  Returns slot or -1.
+__device__ __forceinline__ int hash_find(const int32_t* keys, uint32_t nb_mask, int logNB, int32_t x) {
+    uint32_t b = logNB ? (hash32(x) >> (32 - logNB)) : 0u;
+    for (;;) {
+        const int4 k = *reinterpret_cast<const int4*>(keys + 4 * b);
+        if (k.x == x) return (int)(4 * b);
+        if (k.y == x) return (int)(4 * b + 1);
+        if (k.z == x) return (int)(4 * b + 2);
+        if (k.w == x) return (int)(4 * b + 3);
+        if ((k.x | k.y | k.z | k.w) < 0) return -1;  // a free slot: x is absent
+        b = (b + 1) & nb_mask;
+    }
+}
+
+// continue a lookup at bucket b (after the first bucket was full and did not hold x)
+__device__ __forceinline__ int hash_find_from(const int32_t* keys, uint32_t nb_mask, uint32_t b, int32_t x) {
+    for (;;) {
+        const int4 k = *reinterpret_cast<const int4*>(keys + 4 * b);
+        if (k.x == x) return (int)(4 * b);
+        if (k.y == x) return (int)(4 * b + 1);
+        if (k.z == x) return (int)(4 * b + 2);
+        if (k.w == x) return (int)(4 * b + 3);
+        if ((k.x | k.y | k.z | k.w) < 0) return -1;
+        b = (b + 1) & nb_mask;
+    }
+}
+
+__device__ __forceinline__ void hash_insert(int32_t* keys, uint32_t nb_mask, int logNB, int32_t x) {
+    uint32_t b = logNB ? (hash32(x) >> (32 - logNB)) : 0u;
+    for (;;) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (atomicCAS(&keys[4 * b + k], -1, x) == -1) return;
+        b = (b + 1) & nb_mask;
+    }
+}
+
+__device__ __forceinline__ int sorted_find(const int32_t* keys, int32_t T, int32_t x) {
+    int lo = 0, hi = T;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < T && keys[lo] == x) ? lo : -1;
+}
+
+// A window: 64 consecutive candidates of one tail (lane i takes candidate base + i).
+template <typename OffT>
+struct Win {
+    OffT st;      // tail start in adj
+    int32_t len;  // tail length
+    int32_t base; // first candidate of the window within the tail
+    int32_t j;    // tail index within the wave's chunk (-1: no window)
+};
+
+// One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
+// wig = wave index in the group).  Returns this lane's share of t(v) in `local`.
 template <typename OffT, int PROBE, int NWAVES>
-__device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* keys, uint32_t* cnt,
-                               WaveMeta<OffT>* meta, int gtid, int wig) {
+__device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* keys, uint32_t* cnt, int gtid,
+                               int wig, uint32_t& local) {
     constexpr int gsize = NWAVES * kWave;
     const int lane = lane_id();
     const OffT b0 = a.out_off[v];
@@ -68,21 +120,20 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* key
 
     // ---- stage N+(v)
     int32_t T;
-    int logT = 0;
+    uint32_t nb_mask = 0;
+    int logNB = 0;
     if constexpr (PROBE == TC_LCC_PROBE_HASH) {
         T = 64;
         while (T < 2 * dv) T <<= 1;
-        logT = 31 - __clz(T);
+        const uint32_t nb = (uint32_t)T >> 2;
+        nb_mask = nb - 1;
+        logNB = 31 - __clz(nb);
         for (int s = gtid; s < T; s += gsize) {
             keys[s] = -1;
             cnt[s] = 0;
         }
         group_sync<NWAVES>();
-        for (int j = gtid; j < dv; j += gsize) {
-            const int32_t x = nv[j];
-            uint32_t h = hash_slot(x, logT);
-            while (atomicCAS(&keys[h], -1, x) != -1) h = (h + 1) & (uint32_t)(T - 1);
-        }
+        for (int j = gtid; j < dv; j += gsize) hash_insert(keys, nb_mask, logNB, nv[j]);
     } else {
         T = dv;
         for (int j = gtid; j < dv; j += gsize) {
@@ -92,66 +143,131 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* key
     }
     group_sync<NWAVES>();
 
-    // ---- probe the tails of the in-edges
+    // ---- each wave walks the tails of its chunks of 64 in-edges
     const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
-    uint32_t local = 0;
     for (OffT cb = i0 + (OffT)wig * kWave; cb < i1; cb += (OffT)NWAVES * kWave) {
         const OffT k = cb + lane;
         const bool ok = k < i1;
         int32_t u = 0;
         OffT st = 0;
-        uint32_t len = 0;
+        int32_t len = 0;
         if (ok) {
             u = a.in_u[k];
             st = a.in_start[k];
-            len = (uint32_t)a.in_len[k];
+            len = a.in_len[k];
         }
-        const uint32_t incl = wave_inclusive_scan(len);
-        const uint32_t total = __shfl(incl, kWave - 1, kWave);
-        meta->P[lane] = incl - len;
-        meta->S[lane] = st;
-        meta->E[lane] = 0;
-        wave_lds_sync();
-        for (uint32_t f = lane; f < total; f += kWave) {
-            int s = 0;
+        const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
+        uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
+
+        // window generator over the chunk, all state scalar: tail gj, next base gbase
+        int gj = 0, gbase = 0;
+        OffT gst = 0;
+        int32_t glen = 0;
+        auto fetch_tail = [&]() {
+            if (gj < nk) {
+                const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st & 0xffffffffu), gj);
+                OffT s = (OffT)lo32;
+                if constexpr (sizeof(OffT) == 8) {
+                    const uint32_t hi32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st >> 32), gj);
+                    s = (OffT)(((uint64_t)hi32 << 32) | lo32);
+                }
+                gst = s;
+                glen = __builtin_amdgcn_readlane(len, gj);
+            }
+        };
+        fetch_tail();
+        auto next_win = [&](Win<OffT>& w) {
+            if (gj >= nk) {
+                w.j = -1;
+                w.st = 0;
+                w.len = 1;
+                w.base = 0;
+                return;
+            }
+            w.st = gst;
+            w.len = glen;
+            w.base = gbase;
+            w.j = gj;
+            gbase += kWave;
+            if (gbase >= glen) {
+                gbase = 0;
+                ++gj;
+                fetch_tail();
+            }
+        };
+        // unconditional load (a spent generator yields adj[0]) so that the compiler can wait
+        // for the oldest window only; lanes past the tail re-read its last candidate
+        auto load_win = [&](const Win<OffT>& w) -> int32_t {
+            const int32_t* tp = a.adj + w.st;
+            const uint32_t off = (uint32_t)min(w.base + lane, w.len - 1);
+            return tp[off];
+        };
+
+        // ring of kUnroll windows: slot q holds windows q, q + kUnroll, ...; a slot is probed
+        // and refilled in place, so each load keeps its register until it is consumed
+        Win<OffT> win[kUnroll];
+        int32_t xs[kUnroll];
 #pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
-                if (meta->P[s + step] <= f) s += step;
-            const int32_t x = a.adj[meta->S[s] + (OffT)(f - meta->P[s])];
-            int slot = -1;
-            if constexpr (PROBE == TC_LCC_PROBE_HASH) {
-                uint32_t h = hash_slot(x, logT);
-                for (;;) {
-                    const int32_t kk = keys[h];
-                    if (kk == x) {
-                        slot = (int)h;
-                        break;
+        for (int q = 0; q < kUnroll; ++q) {
+            next_win(win[q]);
+            xs[q] = load_win(win[q]);
+        }
+        int cur_j = 0;       // tail whose hits accumulate in cur_c (windows come in tail order)
+        uint32_t cur_c = 0;  // scalar
+        uint32_t vsum = 0;   // scalar: hits of this wave for t(v)
+        while (win[0].j >= 0) {
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                const Win<OffT> w = win[q];
+                const int32_t x = xs[q];
+                next_win(win[q]);
+                xs[q] = load_win(win[q]);
+                if (w.j >= 0) {
+                    const bool val = w.base + lane < w.len;
+                    int sl = -1;
+                    if constexpr (PROBE == TC_LCC_PROBE_HASH) {
+                        // home bucket and the next one, read together; longer chains are rare
+                        const uint32_t b0 = hash32(x) >> (32 - logNB);
+                        const uint32_t b1 = (b0 + 1) & nb_mask;
+                        const int4 k0 = *reinterpret_cast<const int4*>(keys + 4 * b0);
+                        const int4 k1 = *reinterpret_cast<const int4*>(keys + 4 * b1);
+                        sl = (k1.w == x) ? (int)(4 * b1 + 3) : sl;
+                        sl = (k1.z == x) ? (int)(4 * b1 + 2) : sl;
+                        sl = (k1.y == x) ? (int)(4 * b1 + 1) : sl;
+                        sl = (k1.x == x) ? (int)(4 * b1) : sl;
+                        sl = (k0.w == x) ? (int)(4 * b0 + 3) : sl;
+                        sl = (k0.z == x) ? (int)(4 * b0 + 2) : sl;
+                        sl = (k0.y == x) ? (int)(4 * b0 + 1) : sl;
+                        sl = (k0.x == x) ? (int)(4 * b0) : sl;
+                        const bool go = val && sl < 0 &&
+                                        min(min(min(k0.x, k0.y), min(k0.z, k0.w)),
+                                            min(min(k1.x, k1.y), min(k1.z, k1.w))) >= 0;
+                        if (__ballot(go)) {
+                            if (go) sl = hash_find_from(keys, nb_mask, (b1 + 1) & nb_mask, x);
+                        }
+                    } else {
+                        sl = sorted_find(keys, T, x);
                     }
-                    if (kk < 0) break;
-                    h = (h + 1) & (uint32_t)(T - 1);
+                    const bool hit = val && sl >= 0;
+                    const unsigned long long H = __ballot(hit);
+                    if (w.j != cur_j) {
+                        mine = (lane == cur_j) ? mine + cur_c : mine;
+                        cur_j = w.j;
+                        cur_c = 0;
+                    }
+                    if (H) {
+                        if (hit) atomicAdd(&cnt[sl], 1u);
+                        const uint32_t c = (uint32_t)__popcll(H);
+                        cur_c += c;
+                        vsum += c;
+                    }
                 }
-            } else {
-                int lo = 0, hi = T;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (keys[mid] < x) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo < T && keys[lo] == x) slot = lo;
-            }
-            if (slot >= 0) {
-                atomicAdd(&cnt[slot], 1u);
-                atomicAdd(&meta->E[s], 1u);
-                ++local;
             }
         }
-        wave_lds_sync();
-        const uint32_t c = meta->E[lane];
-        if (ok && c) atomicAdd(&a.t[u], (unsigned long long)c);
-        wave_lds_sync();
+        mine = (lane == cur_j) ? mine + cur_c : mine;
+        local += (lane == 0) ? vsum : 0u;
+        if (ok && mine) atomicAdd(&a.t[u], (unsigned long long)mine);
     }
-    const uint32_t wsum = wave_sum(local);
-    if (lane == 0 && wsum) atomicAdd(&a.t[v], (unsigned long long)wsum);
     group_sync<NWAVES>();
 
     // ---- flush the per-entry counters of N+(v)
@@ -165,12 +281,10 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* key
 template <typename OffT, int PROBE>
 __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
     extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int64_t s_item;
     int32_t* keys = (int32_t*)lds;
     uint32_t* cnt = (uint32_t*)(keys + a.slots);
-    WaveMeta<OffT>* metas = (WaveMeta<OffT>*)(cnt + a.slots);
-    __shared__ int64_t s_item;
     const int w = threadIdx.x / kWave, lane = lane_id();
-    WaveMeta<OffT>* meta = metas + w;
 
     // phase 1: heavy vertices, one block each, heaviest first
     for (;;) {
@@ -179,9 +293,13 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
         const int64_t it = s_item;
         __syncthreads();
         if (it >= a.n_block) break;
-        process_vertex<OffT, PROBE, kWavesPerBlock>(a, a.vlist[it], keys, cnt, meta, threadIdx.x, w);
+        const int32_t v = a.vlist[it];
+        uint32_t local = 0;
+        process_vertex<OffT, PROBE, kWavesPerBlock>(a, v, keys, cnt, threadIdx.x, w, local);
+        const uint32_t ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
     }
-    // phase 2: light vertices, one wave each with its own quarter of the table
+    // phase 2: light vertices, one wave each with its own slice of the table
     const int32_t wslots = a.slots / kWavesPerBlock;
     int32_t* wkeys = keys + w * wslots;
     uint32_t* wcnt = cnt + w * wslots;
@@ -190,18 +308,20 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
         if (lane == 0) it = atomicAdd(&a.ctr[1], 1u);
         it = __shfl(it, 0, kWave);
         if ((int64_t)it >= a.n_wave) break;
-        process_vertex<OffT, PROBE, 1>(a, a.vlist[a.n_block + it], wkeys, wcnt, meta, lane, 0);
+        const int32_t v = a.vlist[a.n_block + it];
+        uint32_t local = 0;
+        process_vertex<OffT, PROBE, 1>(a, v, wkeys, wcnt, lane, 0, local);
+        const uint32_t ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
     }
 }
 
 // Vertices whose N+(v) exceeds the LDS table: binary search straight in N+(v) in
-// global memory, per-entry counts go to t(w) directly.  Never taken when
-// |N+(v)| <= 4096 (hash) or 8192 (sorted).
+// global memory, one wave per in-edge chunk of 64, per-entry counts go to t(w)
+// directly.  Only taken when |N+(v)| > 2048 (hash) or 4096 (sorted).
 template <typename OffT>
-__global__ __launch_bounds__(kCountThreads) void k_count_global(CountArgs<OffT> a) {
-    __shared__ WaveMeta<OffT> metas[kWavesPerBlock];
+__global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
     const int w = threadIdx.x / kWave, lane = lane_id();
-    WaveMeta<OffT>* meta = metas + w;
     for (int64_t it = blockIdx.x; it < a.n_global; it += gridDim.x) {
         const int32_t v = a.vlist[a.n_block + a.n_wave + it];
         const OffT b0 = a.out_off[v];
@@ -209,29 +329,21 @@ __global__ __launch_bounds__(kCountThreads) void k_count_global(CountArgs<OffT> 
         const int32_t* nv = a.adj + b0;
         const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
         uint32_t local = 0;
-        for (OffT cb = i0 + (OffT)w * kWave; cb < i1; cb += (OffT)kWavesPerBlock * kWave) {
+        for (OffT cb = i0 + (OffT)w * kWave; cb < i1; cb += (OffT)4 * kWave) {
             const OffT k = cb + lane;
             const bool ok = k < i1;
             int32_t u = 0;
             OffT st = 0;
-            uint32_t len = 0;
+            int32_t len = 0;
             if (ok) {
                 u = a.in_u[k];
                 st = a.in_start[k];
-                len = (uint32_t)a.in_len[k];
+                len = a.in_len[k];
             }
-            const uint32_t incl = wave_inclusive_scan(len);
-            const uint32_t total = __shfl(incl, kWave - 1, kWave);
-            meta->P[lane] = incl - len;
-            meta->S[lane] = st;
-            meta->E[lane] = 0;
-            wave_lds_sync();
-            for (uint32_t f = lane; f < total; f += kWave) {
-                int s = 0;
-#pragma unroll
-                for (int step = 32; step > 0; step >>= 1)
-                    if (meta->P[s + step] <= f) s += step;
-                const int32_t x = a.adj[meta->S[s] + (OffT)(f - meta->P[s])];
+            // each lane walks its own tail (rare path, kept simple)
+            uint32_t hits = 0;
+            for (int32_t j = 0; j < len; ++j) {
+                const int32_t x = a.adj[st + j];
                 int lo = 0, hi = dv;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
@@ -240,18 +352,14 @@ __global__ __launch_bounds__(kCountThreads) void k_count_global(CountArgs<OffT> 
                 }
                 if (lo < dv && nv[lo] == x) {
                     atomicAdd(&a.t[x], 1ull);
-                    atomicAdd(&meta->E[s], 1u);
-                    ++local;
+                    ++hits;
                 }
             }
-            wave_lds_sync();
-            const uint32_t c = meta->E[lane];
-            if (ok && c) atomicAdd(&a.t[u], (unsigned long long)c);
-            wave_lds_sync();
+            if (hits) atomicAdd(&a.t[u], (unsigned long long)hits);
+            local += hits;
         }
-        const uint32_t wsum = wave_sum(local);
-        if (lane == 0 && wsum) atomicAdd(&a.t[v], (unsigned long long)wsum);
-        __syncthreads();
+        const uint32_t ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
     }
 }
 
@@ -263,7 +371,7 @@ int resolve_probe(int probe, int64_t n) {
 
 template <typename OffT>
 static tc_lcc_status launch_typed(tc_lcc_graph g, hipStream_t st) {
-    const GraphDev& d = g->d;
+    GraphDev& d = g->d;
     CountArgs<OffT> a;
     a.out_off = (const OffT*)d.out_off;
     a.adj = d.adj;
@@ -279,29 +387,29 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, hipStream_t st) {
     a.ctr = d.counters;
     a.slots = d.hash_slots;
     if (d.n_block + d.n_wave > 0) {
-        const size_t lds = (size_t)d.hash_slots * 8 + sizeof(WaveMeta<OffT>) * kWavesPerBlock;
-        int per_cu = 0;
-        if (d.sched_probe == TC_LCC_PROBE_SORTED) {
-            TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count<OffT, TC_LCC_PROBE_SORTED>,
-                                                                 kCountThreads, lds));
-        } else {
-            TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count<OffT, TC_LCC_PROBE_HASH>,
-                                                                 kCountThreads, lds));
+        if (d.hash_slots < 64 * kWavesPerBlock || (d.hash_slots & (d.hash_slots - 1)) != 0) {
+            set_error("count: table of %d slots cannot be split into %d wave slices", d.hash_slots, kWavesPerBlock);
+            return TC_LCC_DEVICE_ERROR;
         }
+        const size_t lds = (size_t)d.hash_slots * 8;
+        auto kern = (d.sched_probe == TC_LCC_PROBE_SORTED) ? k_count<OffT, TC_LCC_PROBE_SORTED>
+                                                           : k_count<OffT, TC_LCC_PROBE_HASH>;
+        int per_cu = 0;
+        TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kCountThreads, lds));
         if (per_cu < 1) per_cu = 1;
         const int64_t want = d.n_block + (d.n_wave + kWavesPerBlock - 1) / kWavesPerBlock;
         int64_t grid = (int64_t)g->ctx->cu_count * per_cu;
         if (grid > want) grid = want;
         if (grid < 1) grid = 1;
-        if (d.sched_probe == TC_LCC_PROBE_SORTED)
-            k_count<OffT, TC_LCC_PROBE_SORTED><<<(unsigned)grid, kCountThreads, lds, st>>>(a);
-        else
-            k_count<OffT, TC_LCC_PROBE_HASH><<<(unsigned)grid, kCountThreads, lds, st>>>(a);
+        kern<<<(unsigned)grid, kCountThreads, lds, st>>>(a);
         TCL_HIP(hipGetLastError());
+        d.count_grid = (int32_t)grid;
+        d.count_lds = (int32_t)lds;
+        d.count_per_cu = per_cu;
     }
     if (d.n_global > 0) {
         const unsigned grid = (unsigned)std::min<int64_t>(d.n_global, (int64_t)g->ctx->cu_count * 4);
-        k_count_global<OffT><<<grid, kCountThreads, 0, st>>>(a);
+        k_count_global<OffT><<<grid, 256, 0, st>>>(a);
         TCL_HIP(hipGetLastError());
     }
     return TC_LCC_OK;

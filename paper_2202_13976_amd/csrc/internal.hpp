@@ -79,6 +79,7 @@ struct GraphDev {
     // profiling events: 0..5 build phase boundaries, 6..9 run phase boundaries
     hipEvent_t ev[10] = {};
     bool prof = false;
+    int32_t count_grid = 0, count_lds = 0, count_per_cu = 0;  // last count launch
     int sched_probe = -1;       // probe the schedule was built for
     uint64_t sched_gen = ~0ull; // tuning generation the schedule was built for
 };
@@ -116,7 +117,7 @@ inline void mark(GraphDev& d, int i, hipStream_t st) {
 
 // radix.hip
 size_t radix_sort_scratch_bytes(size_t n);
-hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int nbits, void* scratch,
+hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
                           hipStream_t st, uint64_t** result);
 
 // build.hip

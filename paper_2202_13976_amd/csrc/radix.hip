@@ -117,9 +117,9 @@ size_t radix_sort_scratch_bytes(size_t n) {
     return (bytes + 255) & ~(size_t)255;
 }
 
-// Sort n keys by their low nbits bits.  Ping-pongs between keys and alt; *result
-// points at whichever holds the sorted keys.
-hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int nbits, void* scratch,
+// Stable sort of n keys by bits [lo_bit, lo_bit + nbits).  Ping-pongs between keys and
+// alt; *result points at whichever holds the sorted keys.
+hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
                           hipStream_t st, uint64_t** result) {
     *result = keys;
     if (n <= 1 || nbits <= 0) return hipSuccess;
@@ -130,7 +130,7 @@ hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int nbits, vo
     uint32_t* sscratch = counts + cnt;
     uint64_t* a = keys;
     uint64_t* b = alt;
-    for (int shift = 0; shift < nbits; shift += 8) {
+    for (int shift = lo_bit; shift < lo_bit + nbits; shift += 8) {
         k_radix_hist<<<tiles, kSortThreads, 0, st>>>(a, n, shift, counts, tiles);
         hipError_t e = exclusive_scan<uint32_t>(ArrayIn<uint32_t>{counts, cnt}, cnt, counts, sscratch, st);
         if (e != hipSuccess) return e;

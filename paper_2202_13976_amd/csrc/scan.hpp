@@ -37,14 +37,19 @@ struct ArrayIn {
     __device__ T operator()(size_t i) const { return i < n ? p[i] : T(0); }
 };
 
+// Tiles are read and written in striped order (element i * 256 + thread), so every
+// global access is coalesced; the per-thread runs of 16 consecutive elements are
+// formed through LDS, padded by one slot per 32 to avoid bank conflicts.
 template <typename T, typename In>
 __global__ __launch_bounds__(kScanThreads) void k_reduce_tiles(In in, size_t n, T* partials) {
     __shared__ T lds[kScanThreads / kWave];
-    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    const size_t base = (size_t)blockIdx.x * kScanTile + threadIdx.x;
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) s += in(base + i);
+    for (int i = 0; i < kScanItems; ++i) {
+        const size_t e = base + (size_t)i * kScanThreads;
+        if (e < n) s += in(e);
+    }
     s = wave_sum(s);
     if (lane_id() == 0) lds[threadIdx.x / kWave] = s;
     __syncthreads();
@@ -55,23 +60,38 @@ __global__ __launch_bounds__(kScanThreads) void k_reduce_tiles(In in, size_t n, 
     }
 }
 
+__device__ __forceinline__ int scan_pad(int e) { return e + (e >> 5); }
+
 template <typename T, typename In>
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(In in, size_t n, const T* tile_off, T* out) {
     __shared__ T lds[kScanThreads / kWave];
-    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    __shared__ T buf[kScanTile + kScanTile / 32];
+    const size_t tile = (size_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int e = i * kScanThreads + threadIdx.x;
+        buf[scan_pad(e)] = (tile + e < n) ? in(tile + e) : T(0);
+    }
+    __syncthreads();
     T v[kScanItems];
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = (base + i < n) ? in(base + i) : T(0);
-        s += v[i];
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = buf[scan_pad(threadIdx.x * kScanItems + j)];
+        s += v[j];
     }
     T total;
     T run = block_exclusive_scan(s, lds, &total) + (tile_off ? tile_off[blockIdx.x] : T(0));
 #pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        buf[scan_pad(threadIdx.x * kScanItems + j)] = run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < n) out[base + i] = run;
-        run += v[i];
+        const int e = i * kScanThreads + threadIdx.x;
+        if (tile + e < n) out[tile + e] = buf[scan_pad(e)];
     }
 }
 
