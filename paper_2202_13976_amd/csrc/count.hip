@@ -107,43 +107,80 @@ struct Win {
     int32_t j;    // tail index within the wave's chunk (-1: no window)
 };
 
-// One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
-// wig = wave index in the group).  Returns this lane's share of t(v) in `local`.
-template <typename OffT, int PROBE, int NWAVES>
-__device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* keys, uint32_t* cnt, int gtid,
-                               int wig, uint32_t& local) {
-    constexpr int gsize = NWAVES * kWave;
-    const int lane = lane_id();
-    const OffT b0 = a.out_off[v];
-    const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
-    const int32_t* nv = a.adj + b0;
-
-    // ---- stage N+(v)
+// LDS view of the staged N+(v) for one probe method.
+//   hash:   keys[T] (-1 = empty) and cnt[T], 4-slot buckets
+//   sorted: keys[dv] = N+(v) and cnt[dv], binary search
+//   bitmap: bm[words] over ranks (v, vmax], first[words] = index in N+(v) of the first
+//           entry in each word, cnt[dv]; the entry index of a hit is first + popcount
+struct Table {
+    int32_t* keys;
+    uint32_t* cnt;
+    uint32_t* bm;
+    uint16_t* first;
     int32_t T;
-    uint32_t nb_mask = 0;
-    int logNB = 0;
-    if constexpr (PROBE == TC_LCC_PROBE_HASH) {
-        T = 64;
-        while (T < 2 * dv) T <<= 1;
-        const uint32_t nb = (uint32_t)T >> 2;
-        nb_mask = nb - 1;
-        logNB = 31 - __clz(nb);
-        for (int s = gtid; s < T; s += gsize) {
-            keys[s] = -1;
-            cnt[s] = 0;
-        }
-        group_sync<NWAVES>();
-        for (int j = gtid; j < dv; j += gsize) hash_insert(keys, nb_mask, logNB, nv[j]);
-    } else {
-        T = dv;
-        for (int j = gtid; j < dv; j += gsize) {
-            keys[j] = nv[j];
-            cnt[j] = 0;
-        }
-    }
-    group_sync<NWAVES>();
+    uint32_t nb_mask;
+    int logNB;
+    int32_t base;   // bitmap: rank v + 1 is bit 0
+    uint32_t span;  // bitmap: ranks v + 1 .. vmax
+    uint32_t words;
+};
 
-    // ---- each wave walks the tails of its chunks of 64 in-edges
+template <int MODE>
+__device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) {
+    bool hit = false;
+    if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
+        const uint32_t i = (uint32_t)(x - tb.base);  // candidates are ranks above v
+        const uint32_t wi = min(i >> 5, tb.words - 1u);
+        const uint32_t word = tb.bm[wi];
+        const uint32_t bit = i & 31u;
+        hit = val && i < tb.span && ((word >> bit) & 1u);
+        if (hit) {
+            const uint32_t pos = (uint32_t)tb.first[wi] + (uint32_t)__popc(word & ((1u << bit) - 1u));
+            atomicAdd(&tb.cnt[pos], 1u);
+        }
+    } else if constexpr (MODE == TC_LCC_PROBE_HASH) {
+        // bucket chain from the home bucket; each matching key bumps its own counter (the
+        // slot is the bucket address plus an immediate offset)
+        uint32_t b = hash32(x) >> (32 - tb.logNB);
+        bool pending = val;
+        for (;;) {
+            const int4 kk = *reinterpret_cast<const int4*>(tb.keys + 4 * b);
+            uint32_t* cb = tb.cnt + 4 * b;
+            if (pending) {
+                if (kk.x == x) {
+                    atomicAdd(cb, 1u);
+                    hit = true;
+                }
+                if (kk.y == x) {
+                    atomicAdd(cb + 1, 1u);
+                    hit = true;
+                }
+                if (kk.z == x) {
+                    atomicAdd(cb + 2, 1u);
+                    hit = true;
+                }
+                if (kk.w == x) {
+                    atomicAdd(cb + 3, 1u);
+                    hit = true;
+                }
+            }
+            // keep looking only past a full bucket that did not hold x
+            pending = pending && !hit && min(min(kk.x, kk.y), min(kk.z, kk.w)) >= 0;
+            if (!__ballot(pending)) break;
+            b = pending ? ((b + 1) & tb.nb_mask) : b;
+        }
+    } else {
+        const int sl = sorted_find(tb.keys, tb.T, x);
+        hit = val && sl >= 0;
+        if (hit) atomicAdd(&tb.cnt[sl], 1u);
+    }
+    return hit;
+}
+
+// Each wave walks the tails of its chunks of 64 in-edges of v and probes every candidate.
+template <typename OffT, int MODE, int NWAVES>
+__device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig, uint32_t& local) {
+    const int lane = lane_id();
     const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
     for (OffT cb = i0 + (OffT)wig * kWave; cb < i1; cb += (OffT)NWAVES * kWave) {
         const OffT k = cb + lane;
@@ -224,31 +261,7 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* key
                 xs[q] = load_win(win[q]);
                 if (w.j >= 0) {
                     const bool val = w.base + lane < w.len;
-                    int sl = -1;
-                    if constexpr (PROBE == TC_LCC_PROBE_HASH) {
-                        // home bucket and the next one, read together; longer chains are rare
-                        const uint32_t b0 = hash32(x) >> (32 - logNB);
-                        const uint32_t b1 = (b0 + 1) & nb_mask;
-                        const int4 k0 = *reinterpret_cast<const int4*>(keys + 4 * b0);
-                        const int4 k1 = *reinterpret_cast<const int4*>(keys + 4 * b1);
-                        sl = (k1.w == x) ? (int)(4 * b1 + 3) : sl;
-                        sl = (k1.z == x) ? (int)(4 * b1 + 2) : sl;
-                        sl = (k1.y == x) ? (int)(4 * b1 + 1) : sl;
-                        sl = (k1.x == x) ? (int)(4 * b1) : sl;
-                        sl = (k0.w == x) ? (int)(4 * b0 + 3) : sl;
-                        sl = (k0.z == x) ? (int)(4 * b0 + 2) : sl;
-                        sl = (k0.y == x) ? (int)(4 * b0 + 1) : sl;
-                        sl = (k0.x == x) ? (int)(4 * b0) : sl;
-                        const bool go = val && sl < 0 &&
-                                        min(min(min(k0.x, k0.y), min(k0.z, k0.w)),
-                                            min(min(k1.x, k1.y), min(k1.z, k1.w))) >= 0;
-                        if (__ballot(go)) {
-                            if (go) sl = hash_find_from(keys, nb_mask, (b1 + 1) & nb_mask, x);
-                        }
-                    } else {
-                        sl = sorted_find(keys, T, x);
-                    }
-                    const bool hit = val && sl >= 0;
+                    const bool hit = probe_one<MODE>(tb, x, val);
                     const unsigned long long H = __ballot(hit);
                     if (w.j != cur_j) {
                         mine = (lane == cur_j) ? mine + cur_c : mine;
@@ -256,7 +269,6 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* key
                         cur_c = 0;
                     }
                     if (H) {
-                        if (hit) atomicAdd(&cnt[sl], 1u);
                         const uint32_t c = (uint32_t)__popcll(H);
                         cur_c += c;
                         vsum += c;
@@ -268,12 +280,93 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, int32_t* key
         local += (lane == 0) ? vsum : 0u;
         if (ok && mine) atomicAdd(&a.t[u], (unsigned long long)mine);
     }
+}
+
+// Bytes of the bitmap layout for `words` bitmap words and dv counters.
+__device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
+    return ((6u * words + 3u) & ~3u) + 4u * (uint32_t)dv;
+}
+
+// One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
+// wig = wave index in the group) with an LDS region of region_bytes.  The probe method is
+// chosen per vertex: the rank bitmap when it fits (AUTO or BITMAP), else the hash; or the
+// sorted list when asked for.  Returns this lane's share of t(v) in `local`.
+template <typename OffT, int PROBE, int NWAVES>
+__device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region, uint32_t region_bytes,
+                               int gtid, int wig, uint32_t& local) {
+    constexpr int gsize = NWAVES * kWave;
+    const OffT b0 = a.out_off[v];
+    const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
+    const int32_t* nv = a.adj + b0;
+
+    Table tb;
+    tb.base = v + 1;
+    int mode;
+    if constexpr (PROBE == TC_LCC_PROBE_SORTED) {
+        mode = TC_LCC_PROBE_SORTED;
+    } else {
+        tb.span = (uint32_t)(nv[dv - 1] - v);
+        tb.words = (tb.span + 31u) >> 5;
+        mode = (PROBE != TC_LCC_PROBE_HASH && bitmap_bytes(tb.words, dv) <= region_bytes) ? TC_LCC_PROBE_BITMAP
+                                                                                           : TC_LCC_PROBE_HASH;
+    }
+
+    // ---- stage N+(v)
+    if (mode == TC_LCC_PROBE_BITMAP) {
+        tb.bm = (uint32_t*)region;
+        tb.first = (uint16_t*)(tb.bm + tb.words);
+        tb.cnt = (uint32_t*)(region + ((6u * tb.words + 3u) & ~3u));
+        for (uint32_t s = gtid; s < tb.words; s += gsize) tb.bm[s] = 0u;
+        for (int j = gtid; j < dv; j += gsize) tb.cnt[j] = 0u;
+        group_sync<NWAVES>();
+        for (int j = gtid; j < dv; j += gsize) {
+            const uint32_t i = (uint32_t)(nv[j] - tb.base);
+            atomicOr(&tb.bm[i >> 5], 1u << (i & 31u));
+            if (j == 0 || ((uint32_t)(nv[j - 1] - tb.base) >> 5) != (i >> 5)) tb.first[i >> 5] = (uint16_t)j;
+        }
+    } else if (mode == TC_LCC_PROBE_HASH) {
+        int32_t T = 64;
+        while (T < 2 * dv) T <<= 1;
+        const uint32_t nb = (uint32_t)T >> 2;
+        tb.T = T;
+        tb.nb_mask = nb - 1;
+        tb.logNB = 31 - __clz(nb);
+        tb.keys = (int32_t*)region;
+        tb.cnt = (uint32_t*)(tb.keys + T);
+        for (int s = gtid; s < T; s += gsize) {
+            tb.keys[s] = -1;
+            tb.cnt[s] = 0;
+        }
+        group_sync<NWAVES>();
+        for (int j = gtid; j < dv; j += gsize) hash_insert(tb.keys, tb.nb_mask, tb.logNB, nv[j]);
+    } else {
+        tb.T = dv;
+        tb.keys = (int32_t*)region;
+        tb.cnt = (uint32_t*)(tb.keys + dv);
+        for (int j = gtid; j < dv; j += gsize) {
+            tb.keys[j] = nv[j];
+            tb.cnt[j] = 0;
+        }
+    }
+    group_sync<NWAVES>();
+
+    // ---- probe the tails of the in-edges
+    if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, v, tb, wig, local);
+    else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, v, tb, wig, local);
+    else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, v, tb, wig, local);
     group_sync<NWAVES>();
 
     // ---- flush the per-entry counters of N+(v)
-    for (int s = gtid; s < T; s += gsize) {
-        const uint32_t c = cnt[s];
-        if (c) atomicAdd(&a.t[keys[s]], (unsigned long long)c);
+    if (mode == TC_LCC_PROBE_HASH) {
+        for (int s = gtid; s < tb.T; s += gsize) {
+            const uint32_t c = tb.cnt[s];
+            if (c) atomicAdd(&a.t[tb.keys[s]], (unsigned long long)c);
+        }
+    } else {
+        for (int j = gtid; j < dv; j += gsize) {
+            const uint32_t c = tb.cnt[j];
+            if (c) atomicAdd(&a.t[nv[j]], (unsigned long long)c);
+        }
     }
     group_sync<NWAVES>();
 }
@@ -282,8 +375,8 @@ template <typename OffT, int PROBE>
 __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int64_t s_item;
-    int32_t* keys = (int32_t*)lds;
-    uint32_t* cnt = (uint32_t*)(keys + a.slots);
+    const uint32_t block_bytes = (uint32_t)a.slots * 8u;
+    const uint32_t wave_bytes = block_bytes / kWavesPerBlock;
     const int w = threadIdx.x / kWave, lane = lane_id();
 
     // phase 1: heavy vertices, one block each, heaviest first
@@ -295,14 +388,12 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
         if (it >= a.n_block) break;
         const int32_t v = a.vlist[it];
         uint32_t local = 0;
-        process_vertex<OffT, PROBE, kWavesPerBlock>(a, v, keys, cnt, threadIdx.x, w, local);
+        process_vertex<OffT, PROBE, kWavesPerBlock>(a, v, lds, block_bytes, threadIdx.x, w, local);
         const uint32_t ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
     }
-    // phase 2: light vertices, one wave each with its own slice of the table
-    const int32_t wslots = a.slots / kWavesPerBlock;
-    int32_t* wkeys = keys + w * wslots;
-    uint32_t* wcnt = cnt + w * wslots;
+    // phase 2: light vertices, one wave each with its own slice of the LDS
+    uint8_t* wregion = lds + (size_t)w * wave_bytes;
     for (;;) {
         unsigned int it = 0;
         if (lane == 0) it = atomicAdd(&a.ctr[1], 1u);
@@ -310,7 +401,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
         if ((int64_t)it >= a.n_wave) break;
         const int32_t v = a.vlist[a.n_block + it];
         uint32_t local = 0;
-        process_vertex<OffT, PROBE, 1>(a, v, wkeys, wcnt, lane, 0, local);
+        process_vertex<OffT, PROBE, 1>(a, v, wregion, wave_bytes, lane, 0, local);
         const uint32_t ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
     }
@@ -363,10 +454,12 @@ __global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
     }
 }
 
+// AUTO and BITMAP both take the rank bitmap where it fits and the hash elsewhere.
 int resolve_probe(int probe, int64_t n) {
     (void)n;
     if (probe == TC_LCC_PROBE_SORTED) return TC_LCC_PROBE_SORTED;
-    return TC_LCC_PROBE_HASH;
+    if (probe == TC_LCC_PROBE_HASH) return TC_LCC_PROBE_HASH;
+    return TC_LCC_PROBE_AUTO;
 }
 
 template <typename OffT>
@@ -391,9 +484,10 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, hipStream_t st) {
             set_error("count: table of %d slots cannot be split into %d wave slices", d.hash_slots, kWavesPerBlock);
             return TC_LCC_DEVICE_ERROR;
         }
-        const size_t lds = (size_t)d.hash_slots * 8;
+        const size_t lds = (size_t)d.hash_slots * 8;  // keys and counters
         auto kern = (d.sched_probe == TC_LCC_PROBE_SORTED) ? k_count<OffT, TC_LCC_PROBE_SORTED>
-                                                           : k_count<OffT, TC_LCC_PROBE_HASH>;
+                    : (d.sched_probe == TC_LCC_PROBE_HASH) ? k_count<OffT, TC_LCC_PROBE_HASH>
+                                                           : k_count<OffT, TC_LCC_PROBE_AUTO>;
         int per_cu = 0;
         TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kCountThreads, lds));
         if (per_cu < 1) per_cu = 1;

@@ -107,7 +107,7 @@ def test_rmat_s23_sampled(ctx):
 
 # ------------------------------------------------------------------ strategies (results never depend on them)
 
-@pytest.mark.parametrize("probe", [pkg.PROBE_HASH, pkg.PROBE_SORTED])
+@pytest.mark.parametrize("probe", [pkg.PROBE_HASH, pkg.PROBE_SORTED, pkg.PROBE_BITMAP])
 @pytest.mark.parametrize("group,wave_max", [(0, 4096), (0, 0), (0, 1 << 40), (1, 0), (2, 0)])
 def test_strategies(ctx, probe, group, wave_max):
     ctx.set_tuning(probe=probe, group=group, wave_work_max=wave_max)
