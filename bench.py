@@ -52,6 +52,13 @@ def count_bytes(info) -> int:
             + (4 * w + 4) * int(info.active_vertices) + 8 * int(info.n))
 
 
+def survey_bytes(info) -> int:
+    """The whole-list streaming figure 4 W + (4 + 2w) m + (2w + 16) n, W = sum over oriented
+    edges (u -> v) of |N+(v)|: bytes a push-style merge would read (reported for comparison)."""
+    w = int(info.offset_bytes)
+    return 4 * int(info.push_words) + (4 + 2 * w) * int(info.m) + (2 * w + 16) * int(info.n)
+
+
 def stored_traffic(kernel_src: str):
     """HBM bytes per count launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel source; otherwise None."""
@@ -91,6 +98,115 @@ def cpu_baseline(n, s, d, target_s: float):
             "seconds": el}
 
 
+def batch_bench(ctx, torch, log_fn, reps: int = 3):
+    """4096 uneven graphs: a loop of single-graph runs against one batched submission."""
+    import numpy as np
+    import synth
+    specs = synth.batch_specs()
+    dev = torch.device("cuda", 0)
+    graphs, tris, lccs = [], [], []
+    m_total = 0
+    log_fn(f"[bench] building {len(specs)} batch graphs")
+    for spec in specs:
+        n, s, d = synth.make(spec)
+        g = ctx.build_csr(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev), offset_bytes=4)
+        graphs.append(g)
+        m_total += int(g.info().m)
+        tris.append(torch.empty(n, dtype=torch.int64, device=dev))
+        lccs.append(torch.empty(n, dtype=torch.float64, device=dev))
+    loop_tris = [torch.empty_like(t) for t in tris]
+
+    def per_graph():
+        for g, t, l in zip(graphs, loop_tris, lccs):
+            g.run(t, l)
+        torch.cuda.synchronize()
+
+    def batched():
+        tk = ctx.batch_submit(graphs, tris, lccs)
+        ctx.batch_poll(tk, block=True)
+
+    per_graph()
+    batched()
+    t_loop, t_batch = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        per_graph()
+        t_loop.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        batched()
+        t_batch.append(time.perf_counter() - t0)
+    same = all(torch.equal(a, b) for a, b in zip(tris, loop_tris))
+    for g in graphs:
+        g.free()
+    tl, tb = float(np.median(t_loop)), float(np.median(t_batch))
+    return {"workload": "4096 graphs, n log-uniform in [64, 16384], half uniform (avg degree 8-32), "
+                        "half R-MAT (EF 8-16), int32 offsets",
+            "graphs": len(specs), "m_total": m_total,
+            "per_graph_ms": tl * 1e3, "batched_ms": tb * 1e3, "speedup": tl / tb,
+            "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same)}
+
+
+def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: float = 0.7):
+    """Poisson request stream over a pool of resident R-MAT graphs: plain server (one request
+    per launch) against the continuous-batching server, same arrivals, same GPU."""
+    import numpy as np
+    import paper_2202_13976_amd as pkg
+    import synth
+    dev = torch.device("cuda", 0)
+    specs = synth.serving_specs(count=64, seed=9)
+    graphs, outs, ms = [], [], []
+    log_fn(f"[bench] building {len(specs)} resident serving graphs")
+    for spec in specs:
+        n, s, d = synth.make(spec)
+        g = ctx.build_csr(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev))
+        graphs.append(g)
+        ms.append(int(g.info().m))
+        outs.append((torch.empty(n, dtype=torch.int64, device=dev), torch.empty(n, dtype=torch.float64, device=dev)))
+    picks = synth.choices(n_warm + n_req, len(graphs), seed=13)
+
+    def run(server, rate):
+        gaps = synth.poisson_gaps(n_warm + n_req, rate, seed=11) if rate else np.zeros(n_warm + n_req)
+        ids = []
+        t0 = time.perf_counter()
+        due = t0
+        for k, gap in zip(picks, gaps):
+            due += gap
+            while time.perf_counter() < due:
+                pass
+            g = graphs[k]
+            ids.append(server.submit(g, *outs[k]))
+        infos = [server.poll(i, block=True) for i in ids]
+        lat = np.array([(x.done_ns - x.arrival_ns) * 1e-6 for x in infos[n_warm:]])
+        first = min(x.arrival_ns for x in infos[n_warm:])
+        last = max(x.done_ns for x in infos[n_warm:])
+        span = (last - first) * 1e-9
+        edges = sum(ms[k] for k in picks[n_warm:])
+        return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "teps": edges / span, "mean_batch": float(np.mean([x.batch_size for x in infos[n_warm:]]))}
+
+    # saturation of the plain path: all requests submitted at once
+    plain = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=1)
+    sat = run(plain, 0.0)
+    plain.close()
+    t_edges = sum(ms[k] for k in picks[n_warm:])
+    sat_rate = n_req * sat["teps"] / t_edges  # requests per second when the plain path is saturated
+    rate = load * sat_rate
+    log_fn(f"[bench] plain saturation {sat_rate:.0f} req/s; offered load {rate:.0f} req/s")
+    res = {"workload": "64 resident R-MAT EF16 graphs, n log-uniform in [2^10, 2^21]; Poisson arrivals, "
+                       "uniform graph choice", "requests": n_req, "warmup": n_warm,
+           "plain_saturation_rps": sat_rate, "offered_rps": rate, "load": load}
+    plain = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=1)
+    res["plain"] = run(plain, rate)
+    plain.close()
+    batched = pkg.Server(ctx, budget_bytes=8 << 30, max_inflight=2, max_batch=4096)
+    res["batched"] = run(batched, rate)
+    res["batched_saturated"] = run(batched, 0.0)
+    batched.close()
+    for g in graphs:
+        g.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +215,8 @@ def main():
     ap.add_argument("--workload", default="rmat_s23_ef16", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB device to device 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -164,6 +282,7 @@ def main():
                      "kernel": "k_count (intersection + scatter)", "alg_bytes_per_launch": alg,
                      "avg_launch_ms": count_ms},
         "run_only_teps": m / (run_ms * 1e-3),
+        "survey_alg_frac": survey_bytes(info) / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
         "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
                   "active_vertices": int(info.active_vertices), "block_vertices": int(info.block_vertices),
@@ -172,6 +291,12 @@ def main():
                   "count_grid": int(info.count_grid), "count_lds_bytes": int(info.count_lds_bytes),
                   "count_blocks_per_cu": int(info.count_blocks_per_cu), "table_slots": int(info.table_slots)},
     }
+    if not args.no_batch:
+        ctx.set_profiling(False)
+        out["batch"] = batch_bench(ctx, torch, log)
+    if not args.no_serve:
+        ctx.set_profiling(False)
+        out["serve"] = serve_bench(ctx, torch, log)
     ctx.close()
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)

@@ -101,6 +101,7 @@ typedef struct {
     int32_t count_lds_bytes;  /* LDS per block of that launch */
     int32_t count_blocks_per_cu; /* resident blocks per compute unit the occupancy query allowed */
     int32_t table_slots;      /* LDS table slots of one block */
+    uint64_t push_words;      /* sum over oriented edges (u -> v) of |N+(v)| (whole-list streaming) */
 } tc_lcc_graph_stats;
 
 tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);
@@ -145,6 +146,43 @@ tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph*
  * *graphs_done (may be NULL) receives how many graphs of the ticket finished.
  * OK releases the ticket; INVALID_ARGUMENT for an unknown ticket. */
 tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int* graphs_done);
+
+/* ------------------------------------------------------------------ serving */
+
+/* A request server over device-resident graphs with continuous batching.
+ * A dispatcher thread admits submitted requests in arrival order while the scratch of
+ * the requests in flight (8 bytes per vertex of each request's graph) stays within
+ * hbm_budget_bytes (0 = no cap), gathers everything admitted at once into one batched
+ * launch, and starts it as soon as fewer than max_inflight batches are running; so
+ * requests that arrive while others run are batched together and overlap with them.
+ * max_inflight = max_batch = 1 gives the plain path: one request at a time through
+ * tc_lcc_run.  Results are identical to tc_lcc_run's for every request. */
+typedef struct tc_lcc_server_s* tc_lcc_server;
+
+typedef struct {
+    int64_t arrival_ns; /* submit time, steady clock */
+    int64_t admit_ns;   /* time the request joined a launch */
+    int64_t done_ns;    /* time its launch was seen complete */
+    int32_t batch_size; /* requests in that launch */
+    int32_t status;     /* tc_lcc_status of the request */
+} tc_lcc_request_info;
+
+tc_lcc_status tc_lcc_server_create(tc_lcc_ctx ctx, uint64_t hbm_budget_bytes, int max_inflight, int max_batch,
+                                   tc_lcc_server* out);
+
+/* Enqueue one request: graph g (built in the server's context), outputs tri/lcc as in
+ * tc_lcc_run (device pointers, kept alive until the request is polled complete).
+ * Returns at once with *request_id.  OVER_BUDGET if the request alone exceeds the budget. */
+tc_lcc_status tc_lcc_server_submit(tc_lcc_server s, tc_lcc_graph g, uint64_t* tri, double* lcc,
+                                   uint64_t* request_id);
+
+/* NOT_READY while the request is queued or running (block == 0), else waits.  On
+ * completion fills *info (may be NULL), releases the id and returns the request's status.
+ * INVALID_ARGUMENT for an unknown id. */
+tc_lcc_status tc_lcc_server_poll(tc_lcc_server s, uint64_t request_id, int block, tc_lcc_request_info* info);
+
+/* Finish every queued and running request, then destroy the server. */
+tc_lcc_status tc_lcc_server_destroy(tc_lcc_server s);
 
 /* ------------------------------------------------------------------ tuning */
 

@@ -38,7 +38,8 @@ class GraphStats(ctypes.Structure):
                 ("kept_in_edges", ctypes.c_int64), ("active_vertices", ctypes.c_int64),
                 ("staged_entries", ctypes.c_int64), ("block_vertices", ctypes.c_int64),
                 ("count_grid", ctypes.c_int32), ("count_lds_bytes", ctypes.c_int32),
-                ("count_blocks_per_cu", ctypes.c_int32), ("table_slots", ctypes.c_int32)]
+                ("count_blocks_per_cu", ctypes.c_int32), ("table_slots", ctypes.c_int32),
+                ("push_words", ctypes.c_uint64)]
 
 
 class Timings(ctypes.Structure):
@@ -56,11 +57,17 @@ class Tuning(ctypes.Structure):
                 ("merge_ratio_x100", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("arrival_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64),
+                ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 _lib = None
 EXPORTS = [
     "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_build_csr", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
+    "tc_lcc_server_create", "tc_lcc_server_submit", "tc_lcc_server_poll", "tc_lcc_server_destroy",
     "tc_lcc_status_string", "tc_lcc_last_error",
 ]
 
@@ -89,6 +96,10 @@ def lib():
     L.tc_lcc_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.tc_lcc_set_profiling.argtypes = [vp, i32]
     L.tc_lcc_graph_timings.argtypes = [vp, ctypes.POINTER(Timings)]
+    L.tc_lcc_server_create.argtypes = [vp, u64, i32, i32, ctypes.POINTER(vp)]
+    L.tc_lcc_server_submit.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64)]
+    L.tc_lcc_server_poll.argtypes = [vp, u64, i32, ctypes.POINTER(RequestInfo)]
+    L.tc_lcc_server_destroy.argtypes = [vp]
     for name in EXPORTS[:-2]:
         getattr(L, name).restype = st
     L.tc_lcc_status_string.argtypes = [st]
@@ -248,6 +259,38 @@ class Context:
     def close(self):
         if self.handle:
             _check(lib().tc_lcc_ctx_destroy(self.handle), "tc_lcc_ctx_destroy")
+            self.handle = None
+
+
+class Server:
+    """Continuous-batching request server (tc_lcc_server); max_inflight = max_batch = 1 is the
+    plain one-request-per-launch path."""
+
+    def __init__(self, ctx: Context, budget_bytes: int = 0, max_inflight: int = 2, max_batch: int = 4096):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().tc_lcc_server_create(ctx.handle, budget_bytes, max_inflight, max_batch, ctypes.byref(h)),
+               "tc_lcc_server_create")
+        self.handle = h
+
+    def submit(self, graph: Graph, tri, lcc=None) -> int:
+        rid = ctypes.c_uint64()
+        _check(lib().tc_lcc_server_submit(self.handle, graph.handle, _dptr(tri), _dptr(lcc), ctypes.byref(rid)),
+               "tc_lcc_server_submit")
+        return int(rid.value)
+
+    def poll(self, request_id: int, block: bool = False):
+        """RequestInfo when the request is complete, None while it is queued or running."""
+        info = RequestInfo()
+        s = lib().tc_lcc_server_poll(self.handle, request_id, 1 if block else 0, ctypes.byref(info))
+        if s == NOT_READY:
+            return None
+        _check(s, "tc_lcc_server_poll")
+        return info
+
+    def close(self):
+        if self.handle:
+            _check(lib().tc_lcc_server_destroy(self.handle), "tc_lcc_server_destroy")
             self.handle = None
 
 

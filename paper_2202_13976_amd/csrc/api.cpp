@@ -303,6 +303,7 @@ extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* o
     out->count_lds_bytes = g->d.count_lds;
     out->count_blocks_per_cu = g->d.count_per_cu;
     out->table_slots = g->d.hash_slots;
+    out->push_words = g->d.push_words;
     return TC_LCC_OK;
 }
 

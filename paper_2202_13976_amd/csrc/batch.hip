@@ -1,21 +1,485 @@
-// Batched path: many graphs in one persistent launch (work queue over (graph, vertex) items).
-#include "internal.hpp"
+// Batched path: many graphs counted by one persistent launch.
+//
+// A batch is a list of device-resident graphs.  Its work items are the active
+// vertices of every graph (each graph's own work list, heaviest first), numbered
+// consecutively across the batch.  Waves of a persistent grid take items from a
+// device queue a few at a time, find the item's graph by a binary search over
+// the per-graph item offsets, and count the vertex exactly as the single-graph
+// kernel does (rank bitmap of N+(v) in LDS where it fits, bucket hash otherwise).
+// Clearing the counters, counting and the LCC epilogue form one HIP graph that
+// is captured once per launch shape and replayed for every batch: all sizes and
+// pointers are read from device memory that each submission rewrites, so the
+// capture does not depend on the batch.  Each context holds a few slots (own
+// stream, descriptors, counters and HIP graph), so batches can overlap on the GPU.
+#include <cstring>
+#include <set>
+
+#include "count_device.hpp"
 
 namespace tcl {
 
-void batch_engine_destroy(tc_lcc_ctx ctx) { (void)ctx; }
+constexpr int kBatchSlots = 4;
+constexpr int kBatchThreads = 256;
+constexpr int kBatchGrab = 8;  // items a wave takes per queue access
+
+struct BatchGraph {
+    const void* out_off;
+    const int32_t* adj;
+    const void* in_off;
+    const int32_t* in_u;
+    const void* in_start;
+    const int32_t* in_len;
+    const int32_t* vlist;
+    const int32_t* order;
+    const int32_t* deg_r;
+    unsigned long long* t;  // this slot's counters for the graph (n entries)
+    unsigned long long* tri;
+    double* lcc;
+    int64_t n;
+    int64_t items;      // active vertices of the graph
+    int64_t item_base;  // first item of the graph in the batch
+};
+
+struct BatchHeader {
+    int32_t count;        // graphs in the batch
+    int32_t count4;       // graphs [0, count4) use 4-byte offsets, the rest 8-byte ones
+    int64_t items4;       // items of the 4-byte graphs
+    int64_t items;        // all items
+    uint32_t region;      // LDS bytes per wave
+    uint32_t seq;         // submission number, written to the done flags
+    unsigned int queue[2];
+};
+
+__global__ void k_batch_zero(const BatchGraph* __restrict__ gs, BatchHeader* h) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) h->queue[threadIdx.x] = 0u;
+    const int count = h->count;
+    for (int g = blockIdx.x; g < count; g += gridDim.x) {
+        unsigned long long* t = gs[g].t;
+        const int64_t n = gs[g].n;
+        for (int64_t r = threadIdx.x; r < n; r += blockDim.x) t[r] = 0ull;
+    }
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph* __restrict__ gs, BatchHeader* h,
+                                                               int which) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t rb = h->region;
+    uint8_t* region = lds + (size_t)w * rb;
+    const int64_t lo = which ? h->items4 : 0, hi = which ? h->items : h->items4;
+    const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
+    for (;;) {
+        unsigned int it = 0;
+        if (lane == 0) it = atomicAdd(&h->queue[which], (unsigned int)kBatchGrab);
+        it = __shfl(it, 0, kWave);
+        int64_t item = lo + (int64_t)it;
+        if (item >= hi) break;
+        const int64_t end = min(item + kBatchGrab, hi);
+        // graph of the first item: last g with item_base <= item
+        int ga = g_lo, gb = g_hi - 1;
+        while (ga < gb) {
+            const int mid = (ga + gb + 1) >> 1;
+            if (gs[mid].item_base <= item) ga = mid;
+            else gb = mid - 1;
+        }
+        int g = __builtin_amdgcn_readfirstlane(ga);
+        for (; item < end; ++item) {
+            while (item >= gs[g].item_base + gs[g].items) ++g;  // graphs with no items are skipped
+            const BatchGraph& G = gs[g];
+            CountArgs<OffT> a;
+            a.out_off = (const OffT*)G.out_off;
+            a.adj = G.adj;
+            a.in_off = (const OffT*)G.in_off;
+            a.in_u = G.in_u;
+            a.in_start = (const OffT*)G.in_start;
+            a.in_len = G.in_len;
+            a.vlist = G.vlist;
+            a.n_block = a.n_wave = a.n_global = 0;
+            a.t = G.t;
+            a.ctr = nullptr;
+            a.slots = 0;
+            const int32_t v = G.vlist[item - G.item_base];
+            uint32_t local = 0;
+            process_vertex<OffT, TC_LCC_PROBE_AUTO, 1>(a, v, region, rb, lane, 0, local);
+            const uint32_t ws = wave_sum(local);
+            if (lane == 0 && ws) atomicAdd(&G.t[v], (unsigned long long)ws);
+        }
+    }
+}
+
+// Eq. 2 per vertex, as the single-graph epilogue; each graph then raises its done flag.
+__global__ void k_batch_epilogue(const BatchGraph* __restrict__ gs, const BatchHeader* h,
+                                 unsigned int* __restrict__ done) {
+    const int count = h->count;
+    const unsigned int seq = h->seq;
+    for (int g = blockIdx.x; g < count; g += gridDim.x) {
+        const BatchGraph& G = gs[g];
+        for (int64_t r = threadIdx.x; r < G.n; r += blockDim.x) {
+            const int32_t v = G.order[r];
+            const unsigned long long tv = G.t[r];
+            const int64_t d = G.deg_r[r];
+            G.tri[v] = tv;
+            if (G.lcc) {
+                double x = 0.0;
+                if (d >= 2) x = (double)(2ull * tv) / (double)((unsigned long long)d * (unsigned long long)(d - 1));
+                G.lcc[v] = x;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence_system();
+            done[g] = seq;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    uint64_t ticket = 0;
+    uint32_t seq = 0;
+    std::vector<tc_lcc_graph> graphs;
+    int count = 0;
+    // device buffers (from the context pool)
+    BatchGraph* d_graphs = nullptr;
+    BatchHeader* d_hdr = nullptr;
+    unsigned long long* d_scratch = nullptr;
+    size_t cap_graphs = 0, cap_scratch = 0;
+    // pinned host staging and done flags
+    BatchGraph* h_graphs = nullptr;
+    BatchHeader* h_hdr = nullptr;
+    unsigned int* h_done = nullptr;
+    unsigned int* d_done = nullptr;
+    size_t cap_done = 0;
+    // captured launches, keyed by (region class, which kernels)
+    std::map<uint64_t, hipGraphExec_t> execs;
+};
+
+struct Engine {
+    Slot slots[kBatchSlots];
+    uint64_t next_ticket = 1;
+    uint32_t next_seq = 1;
+    std::mutex mu;
+    std::map<uint64_t, int> completed;  // tickets finished before their poll: graphs done
+};
+
+Engine* engine(tc_lcc_ctx ctx) {
+    if (!ctx->batch) ctx->batch = new Engine();
+    return (Engine*)ctx->batch;
+}
+
+void drop_execs(Slot& s) {
+    for (auto& kv : s.execs) (void)hipGraphExecDestroy(kv.second);
+    s.execs.clear();
+}
+
+tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t scratch) {
+    Pool* pool = ctx->pool.get();
+    bool changed = false;
+    if (graphs > s.cap_graphs) {
+        size_t cap = std::max<size_t>(graphs, 2 * s.cap_graphs);
+        if (s.d_graphs) pool->release(s.d_graphs);
+        void* p = nullptr;
+        tc_lcc_status st = pool->alloc(cap * sizeof(BatchGraph), &p);
+        if (st != TC_LCC_OK) return st;
+        s.d_graphs = (BatchGraph*)p;
+        if (s.h_graphs) (void)hipHostFree(s.h_graphs);
+        s.h_graphs = nullptr;
+        if (hipHostMalloc((void**)&s.h_graphs, cap * sizeof(BatchGraph), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("batch: pinned host allocation failed");
+            return TC_LCC_OUT_OF_MEMORY;
+        }
+        if (s.h_done) (void)hipHostFree(s.h_done);
+        s.h_done = nullptr;
+        if (hipHostMalloc((void**)&s.h_done, cap * sizeof(unsigned int), hipHostMallocMapped) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&s.d_done, s.h_done, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("batch: mapped host allocation failed");
+            return TC_LCC_OUT_OF_MEMORY;
+        }
+        memset(s.h_done, 0, cap * sizeof(unsigned int));
+        s.cap_graphs = cap;
+        s.cap_done = cap;
+        changed = true;
+    }
+    if (!s.d_hdr) {
+        void* p = nullptr;
+        tc_lcc_status st = pool->alloc(sizeof(BatchHeader), &p);
+        if (st != TC_LCC_OK) return st;
+        s.d_hdr = (BatchHeader*)p;
+        if (hipHostMalloc((void**)&s.h_hdr, sizeof(BatchHeader), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("batch: pinned host allocation failed");
+            return TC_LCC_OUT_OF_MEMORY;
+        }
+        changed = true;
+    }
+    if (scratch > s.cap_scratch) {
+        size_t cap = std::max<size_t>(scratch, s.cap_scratch + s.cap_scratch / 2);
+        if (s.d_scratch) pool->release(s.d_scratch);
+        void* p = nullptr;
+        tc_lcc_status st = pool->alloc(cap * sizeof(unsigned long long), &p);
+        if (st != TC_LCC_OK) return st;
+        s.d_scratch = (unsigned long long*)p;
+        s.cap_scratch = cap;
+    }
+    if (changed) drop_execs(s);
+    return TC_LCC_OK;
+}
+
+// LDS bytes per wave that every vertex of g fits: the rank bitmap over all n ranks if it
+// fits, else the bucket hash for the largest out-list.
+uint32_t region_need(const GraphDev& d) {
+    const uint32_t words = (uint32_t)((d.n + 31) / 32);
+    const uint32_t bm = ((6u * words + 3u) & ~3u) + 4u * (uint32_t)d.max_dplus;
+    int32_t T = 64;
+    while (T < 2 * d.max_dplus) T <<= 1;
+    const uint32_t hs = 8u * (uint32_t)T;
+    return std::min(bm, hs);
+}
+
+constexpr uint32_t kRegionClasses[] = {2048, 4096, 8192};
+
+tc_lcc_status capture(Slot& s, uint32_t region, bool has4, bool has8, int cu_count, hipGraphExec_t* out) {
+    const uint64_t key = ((uint64_t)region << 2) | (has4 ? 1u : 0u) | (has8 ? 2u : 0u);
+    auto it = s.execs.find(key);
+    if (it != s.execs.end()) {
+        *out = it->second;
+        return TC_LCC_OK;
+    }
+    const size_t lds = (size_t)region * (kBatchThreads / kWave);
+    int per4 = 0, per8 = 0;
+    TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per4, k_batch_count<int32_t>, kBatchThreads, lds));
+    TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per8, k_batch_count<int64_t>, kBatchThreads, lds));
+    const unsigned g4 = (unsigned)(cu_count * std::max(per4, 1));
+    const unsigned g8 = (unsigned)(cu_count * std::max(per8, 1));
+    hipGraph_t graph = nullptr;
+    TCL_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
+    k_batch_zero<<<2048, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr);
+    if (has4) k_batch_count<int32_t><<<g4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
+    if (has8) k_batch_count<int64_t><<<g8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
+    k_batch_epilogue<<<2048, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
+    hipError_t e = hipStreamEndCapture(s.stream, &graph);
+    if (e != hipSuccess) {
+        set_error("batch: stream capture failed: %s", hipGetErrorString(e));
+        return TC_LCC_DEVICE_ERROR;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        set_error("batch: graph instantiation failed: %s", hipGetErrorString(e));
+        return TC_LCC_DEVICE_ERROR;
+    }
+    s.execs[key] = exec;
+    *out = exec;
+    return TC_LCC_OK;
+}
+
+void finish_slot(Slot& s) {
+    for (tc_lcc_graph g : s.graphs) g->inflight--;
+    s.graphs.clear();
+    s.busy = false;
+}
+
+}  // namespace
+
+void batch_engine_destroy(tc_lcc_ctx ctx) {
+    if (!ctx->batch) return;
+    Engine* e = (Engine*)ctx->batch;
+    for (Slot& s : e->slots) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        drop_execs(s);
+        if (s.d_graphs) ctx->pool->release(s.d_graphs);
+        if (s.d_hdr) ctx->pool->release(s.d_hdr);
+        if (s.d_scratch) ctx->pool->release(s.d_scratch);
+        if (s.h_graphs) (void)hipHostFree(s.h_graphs);
+        if (s.h_hdr) (void)hipHostFree(s.h_hdr);
+        if (s.h_done) (void)hipHostFree(s.h_done);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+    }
+    delete e;
+    ctx->batch = nullptr;
+}
 
 }  // namespace tcl
 
+using namespace tcl;
+
 extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs,
                                              uint64_t* const* tri, double* const* lcc, tc_lcc_ticket* out) {
-    (void)ctx; (void)count; (void)graphs; (void)tri; (void)lcc; (void)out;
-    tcl::set_error("tc_lcc_batch_submit: not built yet");
-    return TC_LCC_UNSUPPORTED;
+    if (!ctx || count <= 0 || !graphs || !tri || !out) {
+        set_error("tc_lcc_batch_submit: null argument or count <= 0");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!graphs[i] || graphs[i]->ctx != ctx || !tri[i]) {
+            set_error("tc_lcc_batch_submit: graph %d is null, from another context, or has no output", i);
+            return TC_LCC_INVALID_ARGUMENT;
+        }
+    }
+    TCL_HIP(hipSetDevice(ctx->device));
+    Engine* e = engine(ctx);
+    std::unique_lock<std::mutex> lk(e->mu);
+    // a free slot; if all are busy, wait for the oldest submission
+    Slot* s = nullptr;
+    for (Slot& c : e->slots)
+        if (!c.busy) {
+            s = &c;
+            break;
+        }
+    if (!s) {
+        Slot* oldest = &e->slots[0];
+        for (Slot& c : e->slots)
+            if (c.ticket < oldest->ticket) oldest = &c;
+        TCL_HIP(hipEventSynchronize(oldest->ev));
+        e->completed[oldest->ticket] = oldest->count;
+        finish_slot(*oldest);
+        ctx->tickets_inflight--;
+        s = oldest;
+    }
+    if (!s->stream) {
+        TCL_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        TCL_HIP(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
+    }
+
+    // order: 4-byte-offset graphs first, then 8-byte ones; graphs with vertices beyond the
+    // LDS table (global-memory path) run through the single-graph launches instead
+    std::vector<int> ord4, ord8, solo;
+    uint32_t need = 0;
+    size_t scratch = 0;
+    for (int i = 0; i < count; ++i) {
+        const GraphDev& d = graphs[i]->d;
+        const uint32_t r = region_need(d);
+        if (d.n_global > 0 || r > kRegionClasses[2]) {
+            solo.push_back(i);
+            continue;
+        }
+        need = std::max(need, r);
+        scratch += (size_t)d.n;
+        (d.off_bytes == 4 ? ord4 : ord8).push_back(i);
+    }
+    uint32_t region = kRegionClasses[2];
+    for (uint32_t c : kRegionClasses)
+        if (need <= c) {
+            region = c;
+            break;
+        }
+    const int nb = (int)(ord4.size() + ord8.size());
+    tc_lcc_status st = ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), std::max<size_t>(scratch, 1));
+    if (st != TC_LCC_OK) return st;
+
+    const uint32_t seq = e->next_seq++;
+    int64_t item = 0, items4 = 0;
+    size_t soff = 0;
+    int k = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i : (pass == 0 ? ord4 : ord8)) {
+            const GraphDev& d = graphs[i]->d;
+            BatchGraph& b = s->h_graphs[k++];
+            b.out_off = d.out_off;
+            b.adj = d.adj;
+            b.in_off = d.in_off;
+            b.in_u = d.in_u;
+            b.in_start = d.in_start;
+            b.in_len = d.in_len;
+            b.vlist = d.vlist;
+            b.order = d.order;
+            b.deg_r = d.deg_r;
+            b.t = s->d_scratch + soff;
+            b.tri = (unsigned long long*)tri[i];
+            b.lcc = lcc ? lcc[i] : nullptr;
+            b.n = d.n;
+            b.items = d.n_block + d.n_wave;
+            b.item_base = item;
+            item += b.items;
+            soff += (size_t)d.n;
+        }
+        if (pass == 0) items4 = item;
+    }
+    s->h_hdr->count = nb;
+    s->h_hdr->count4 = (int32_t)ord4.size();
+    s->h_hdr->items4 = items4;
+    s->h_hdr->items = item;
+    s->h_hdr->region = region;
+    s->h_hdr->seq = seq;
+    s->h_hdr->queue[0] = s->h_hdr->queue[1] = 0;
+
+    if (nb > 0) {
+        hipGraphExec_t exec = nullptr;
+        st = capture(*s, region, !ord4.empty(), !ord8.empty(), ctx->cu_count, &exec);
+        if (st != TC_LCC_OK) return st;
+        TCL_HIP(hipMemcpyAsync(s->d_graphs, s->h_graphs, (size_t)nb * sizeof(BatchGraph), hipMemcpyHostToDevice,
+                               s->stream));
+        TCL_HIP(hipMemcpyAsync(s->d_hdr, s->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s->stream));
+        TCL_HIP(hipGraphLaunch(exec, s->stream));
+    }
+    // graphs that need the global-memory path: the single-graph launches, on this slot's stream
+    for (int i : solo) {
+        lk.unlock();
+        st = tc_lcc_run(graphs[i], tri[i], lcc ? lcc[i] : nullptr, s->stream);
+        lk.lock();
+        if (st != TC_LCC_OK) return st;
+    }
+    TCL_HIP(hipEventRecord(s->ev, s->stream));
+    s->busy = true;
+    s->seq = seq;
+    s->count = count;
+    s->ticket = e->next_ticket++;
+    s->graphs.assign(graphs, graphs + count);
+    for (int i = 0; i < count; ++i) graphs[i]->inflight++;
+    ctx->tickets_inflight++;
+    *out = s->ticket;
+    return TC_LCC_OK;
 }
 
 extern "C" tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int* graphs_done) {
-    (void)ctx; (void)t; (void)block; (void)graphs_done;
-    tcl::set_error("tc_lcc_batch_poll: unknown ticket");
+    if (!ctx) {
+        set_error("tc_lcc_batch_poll: null context");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (!ctx->batch) {
+        set_error("tc_lcc_batch_poll: unknown ticket %llu", (unsigned long long)t);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    TCL_HIP(hipSetDevice(ctx->device));
+    Engine* e = (Engine*)ctx->batch;
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto done_it = e->completed.find(t);
+    if (done_it != e->completed.end()) {
+        if (graphs_done) *graphs_done = done_it->second;
+        e->completed.erase(done_it);
+        return TC_LCC_OK;
+    }
+    for (Slot& s : e->slots) {
+        if (!s.busy || s.ticket != t) continue;
+        hipError_t q = block ? hipEventSynchronize(s.ev) : hipEventQuery(s.ev);
+        if (q == hipErrorNotReady) {
+            if (graphs_done) {
+                int c = 0;
+                const int nb = (int)std::min<size_t>(s.cap_done, (size_t)s.count);
+                for (int i = 0; i < nb; ++i) c += (__atomic_load_n(&s.h_done[i], __ATOMIC_ACQUIRE) == s.seq);
+                *graphs_done = c;
+            }
+            return TC_LCC_NOT_READY;
+        }
+        if (q != hipSuccess) {
+            set_error("tc_lcc_batch_poll: %s", hipGetErrorString(q));
+            return TC_LCC_DEVICE_ERROR;
+        }
+        if (graphs_done) *graphs_done = s.count;
+        finish_slot(s);
+        ctx->tickets_inflight--;
+        return TC_LCC_OK;
+    }
+    set_error("tc_lcc_batch_poll: unknown ticket %llu", (unsigned long long)t);
     return TC_LCC_INVALID_ARGUMENT;
 }

@@ -196,17 +196,20 @@ __global__ void k_work(const OffT* __restrict__ in_off, const uint64_t* __restri
 }
 
 // stats[0] = max |N+|, stats[1] = max degree, stats[2] = sum of work (wedges),
-// stats[3] = sum of |N+(v)| over vertices with work (entries staged in LDS)
+// stats[3] = sum of |N+(v)| over vertices with work (entries staged in LDS),
+// stats[4] = sum over oriented edges (u -> v) of |N+(v)| = sum_v (d(v) - |N+(v)|) |N+(v)|
 __global__ void k_stats(const int32_t* __restrict__ dplus, const int32_t* __restrict__ deg_r,
                         const unsigned long long* __restrict__ work, int64_t n, unsigned long long* stats) {
-    __shared__ unsigned long long s[4][kB / kWave];
-    unsigned long long a = 0, b = 0, c = 0, e = 0;
+    __shared__ unsigned long long s[5][kB / kWave];
+    unsigned long long a = 0, b = 0, c = 0, e = 0, f = 0;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         const unsigned long long wr = work[r];
-        a = max(a, (unsigned long long)dplus[r]);
+        const unsigned long long dp = (unsigned long long)dplus[r];
+        a = max(a, dp);
         b = max(b, (unsigned long long)deg_r[r]);
         c += wr;
-        if (wr) e += (unsigned long long)dplus[r];
+        if (wr) e += dp;
+        f += ((unsigned long long)deg_r[r] - dp) * dp;
     }
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) {
@@ -214,6 +217,7 @@ __global__ void k_stats(const int32_t* __restrict__ dplus, const int32_t* __rest
         b = max(b, (unsigned long long)__shfl_xor(b, d, kWave));
         c += __shfl_xor(c, d, kWave);
         e += __shfl_xor(e, d, kWave);
+        f += __shfl_xor(f, d, kWave);
     }
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
@@ -221,6 +225,7 @@ __global__ void k_stats(const int32_t* __restrict__ dplus, const int32_t* __rest
         s[1][w] = b;
         s[2][w] = c;
         s[3][w] = e;
+        s[4][w] = f;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -228,16 +233,19 @@ __global__ void k_stats(const int32_t* __restrict__ dplus, const int32_t* __rest
         b = 0;
         c = 0;
         e = 0;
+        f = 0;
         for (int i = 0; i < kB / kWave; ++i) {
             a = max(a, s[0][i]);
             b = max(b, s[1][i]);
             c += s[2][i];
             e += s[3][i];
+            f += s[4][i];
         }
         atomicMax(&stats[0], a);
         atomicMax(&stats[1], b);
         atomicAdd(&stats[2], c);
         atomicAdd(&stats[3], e);
+        atomicAdd(&stats[4], f);
     }
 }
 
@@ -475,17 +483,18 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_TRY(keep(g, 64, &d.counters));
     TCL_TRY(keep(g, N, &d.vlist));
     unsigned long long* stats;
-    TCL_TRY(tmp.get(4, &stats));
-    TCL_HIP(fill<unsigned long long>(stats, 4, 0ull, st));
+    TCL_TRY(tmp.get(8, &stats));
+    TCL_HIP(fill<unsigned long long>(stats, 8, 0ull, st));
     k_stats<<<grid_for(N, kB, 2048), kB, 0, st>>>(d.dplus, d.deg_r, (const unsigned long long*)d.work, n, stats);
     TCL_HIP(hipGetLastError());
-    unsigned long long hs[4] = {0, 0, 0, 0};
+    unsigned long long hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     TCL_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
     TCL_HIP(hipStreamSynchronize(st));
     d.max_dplus = (int32_t)hs[0];
     d.max_deg = (int64_t)hs[1];
     d.wedges = hs[2];
     d.staged = hs[3];
+    d.push_words = hs[4];
     return TC_LCC_OK;
 }
 

@@ -1,0 +1,357 @@
+// Device code shared by the single-graph and the batched count kernels: the staged
+// N+(v) (rank bitmap, bucket hash or sorted list in LDS), the tail walk that probes
+// every candidate, and the per-triangle scatter.  See count.hip for the method.
+#pragma once
+
+#include "internal.hpp"
+
+namespace tcl {
+
+constexpr int kUnroll = 4;  // prefetched windows of 64 candidates
+
+template <typename OffT>
+struct CountArgs {
+    const OffT* out_off;
+    const int32_t* adj;
+    const OffT* in_off;
+    const int32_t* in_u;
+    const OffT* in_start;
+    const int32_t* in_len;
+    const int32_t* vlist;
+    int64_t n_block, n_wave, n_global;
+    unsigned long long* t;
+    unsigned int* ctr;
+    int32_t slots;  // table slots of a block (power of two, >= 256)
+};
+
+// bucket hash: high bits of a 24x24-bit product (one full-rate multiply)
+__device__ __forceinline__ uint32_t hash32(int32_t x) { return __umul24((uint32_t)x, 0x9E3779u); }
+
+template <int NWAVES>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (NWAVES > 1) __syncthreads();
+    else wave_lds_sync();
+}
+
+// Bucketed open addressing: 4 slots per bucket read with one 16-byte LDS load; a key
+// lives in the first bucket with room from its hash bucket on.  Returns slot or -1.
+__device__ __forceinline__ int hash_find(const int32_t* keys, uint32_t nb_mask, int logNB, int32_t x) {
+    uint32_t b = logNB ? (hash32(x) >> (32 - logNB)) : 0u;
+    for (;;) {
+        const int4 k = *reinterpret_cast<const int4*>(keys + 4 * b);
+        if (k.x == x) return (int)(4 * b);
+        if (k.y == x) return (int)(4 * b + 1);
+        if (k.z == x) return (int)(4 * b + 2);
+        if (k.w == x) return (int)(4 * b + 3);
+        if ((k.x | k.y | k.z | k.w) < 0) return -1;  // a free slot: x is absent
+        b = (b + 1) & nb_mask;
+    }
+}
+
+// continue a lookup at bucket b (after the first bucket was full and did not hold x)
+__device__ __forceinline__ int hash_find_from(const int32_t* keys, uint32_t nb_mask, uint32_t b, int32_t x) {
+    for (;;) {
+        const int4 k = *reinterpret_cast<const int4*>(keys + 4 * b);
+        if (k.x == x) return (int)(4 * b);
+        if (k.y == x) return (int)(4 * b + 1);
+        if (k.z == x) return (int)(4 * b + 2);
+        if (k.w == x) return (int)(4 * b + 3);
+        if ((k.x | k.y | k.z | k.w) < 0) return -1;
+        b = (b + 1) & nb_mask;
+    }
+}
+
+__device__ __forceinline__ void hash_insert(int32_t* keys, uint32_t nb_mask, int logNB, int32_t x) {
+    uint32_t b = logNB ? (hash32(x) >> (32 - logNB)) : 0u;
+    for (;;) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (atomicCAS(&keys[4 * b + k], -1, x) == -1) return;
+        b = (b + 1) & nb_mask;
+    }
+}
+
+__device__ __forceinline__ int sorted_find(const int32_t* keys, int32_t T, int32_t x) {
+    int lo = 0, hi = T;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < T && keys[lo] == x) ? lo : -1;
+}
+
+// A window: 64 consecutive candidates of one tail (lane i takes candidate base + i).
+template <typename OffT>
+struct Win {
+    OffT st;      // tail start in adj
+    int32_t len;  // tail length
+    int32_t base; // first candidate of the window within the tail
+    int32_t j;    // tail index within the wave's chunk (-1: no window)
+};
+
+// LDS view of the staged N+(v) for one probe method.
+//   hash:   keys[T] (-1 = empty) and cnt[T], 4-slot buckets
+//   sorted: keys[dv] = N+(v) and cnt[dv], binary search
+//   bitmap: bm[words] over ranks (v, vmax], first[words] = index in N+(v) of the first
+//           entry in each word, cnt[dv]; the entry index of a hit is first + popcount
+struct Table {
+    int32_t* keys;
+    uint32_t* cnt;
+    uint32_t* bm;
+    uint16_t* first;
+    int32_t T;
+    uint32_t nb_mask;
+    int logNB;
+    int32_t base;   // bitmap: rank v + 1 is bit 0
+    uint32_t span;  // bitmap: ranks v + 1 .. vmax
+    uint32_t words;
+};
+
+template <int MODE>
+__device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) {
+    bool hit = false;
+    if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
+        const uint32_t i = (uint32_t)(x - tb.base);  // candidates are ranks above v
+        const uint32_t wi = min(i >> 5, tb.words - 1u);
+        const uint32_t word = tb.bm[wi];
+        const uint32_t bit = i & 31u;
+        hit = val && i < tb.span && ((word >> bit) & 1u);
+        if (hit) {
+            const uint32_t pos = (uint32_t)tb.first[wi] + (uint32_t)__popc(word & ((1u << bit) - 1u));
+            atomicAdd(&tb.cnt[pos], 1u);
+        }
+    } else if constexpr (MODE == TC_LCC_PROBE_HASH) {
+        // bucket chain from the home bucket; each matching key bumps its own counter (the
+        // slot is the bucket address plus an immediate offset)
+        uint32_t b = hash32(x) >> (32 - tb.logNB);
+        bool pending = val;
+        for (;;) {
+            const int4 kk = *reinterpret_cast<const int4*>(tb.keys + 4 * b);
+            uint32_t* cb = tb.cnt + 4 * b;
+            if (pending) {
+                if (kk.x == x) {
+                    atomicAdd(cb, 1u);
+                    hit = true;
+                }
+                if (kk.y == x) {
+                    atomicAdd(cb + 1, 1u);
+                    hit = true;
+                }
+                if (kk.z == x) {
+                    atomicAdd(cb + 2, 1u);
+                    hit = true;
+                }
+                if (kk.w == x) {
+                    atomicAdd(cb + 3, 1u);
+                    hit = true;
+                }
+            }
+            // keep looking only past a full bucket that did not hold x
+            pending = pending && !hit && min(min(kk.x, kk.y), min(kk.z, kk.w)) >= 0;
+            if (!__ballot(pending)) break;
+            b = pending ? ((b + 1) & tb.nb_mask) : b;
+        }
+    } else {
+        const int sl = sorted_find(tb.keys, tb.T, x);
+        hit = val && sl >= 0;
+        if (hit) atomicAdd(&tb.cnt[sl], 1u);
+    }
+    return hit;
+}
+
+// Each wave walks the tails of its chunks of 64 in-edges of v and probes every candidate.
+template <typename OffT, int MODE, int NWAVES>
+__device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig, uint32_t& local) {
+    const int lane = lane_id();
+    const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
+    for (OffT cb = i0 + (OffT)wig * kWave; cb < i1; cb += (OffT)NWAVES * kWave) {
+        const OffT k = cb + lane;
+        const bool ok = k < i1;
+        int32_t u = 0;
+        OffT st = 0;
+        int32_t len = 0;
+        if (ok) {
+            u = a.in_u[k];
+            st = a.in_start[k];
+            len = a.in_len[k];
+        }
+        const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
+        uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
+
+        // window generator over the chunk, all state scalar: tail gj, next base gbase
+        int gj = 0, gbase = 0;
+        OffT gst = 0;
+        int32_t glen = 0;
+        auto fetch_tail = [&]() {
+            if (gj < nk) {
+                const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st & 0xffffffffu), gj);
+                OffT s = (OffT)lo32;
+                if constexpr (sizeof(OffT) == 8) {
+                    const uint32_t hi32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st >> 32), gj);
+                    s = (OffT)(((uint64_t)hi32 << 32) | lo32);
+                }
+                gst = s;
+                glen = __builtin_amdgcn_readlane(len, gj);
+            }
+        };
+        fetch_tail();
+        auto next_win = [&](Win<OffT>& w) {
+            if (gj >= nk) {
+                w.j = -1;
+                w.st = 0;
+                w.len = 1;
+                w.base = 0;
+                return;
+            }
+            w.st = gst;
+            w.len = glen;
+            w.base = gbase;
+            w.j = gj;
+            gbase += kWave;
+            if (gbase >= glen) {
+                gbase = 0;
+                ++gj;
+                fetch_tail();
+            }
+        };
+        // unconditional load (a spent generator yields adj[0]) so that the compiler can wait
+        // for the oldest window only; lanes past the tail re-read its last candidate
+        auto load_win = [&](const Win<OffT>& w) -> int32_t {
+            const int32_t* tp = a.adj + w.st;
+            const uint32_t off = (uint32_t)min(w.base + lane, w.len - 1);
+            return tp[off];
+        };
+
+        // ring of kUnroll windows: slot q holds windows q, q + kUnroll, ...; a slot is probed
+        // and refilled in place, so each load keeps its register until it is consumed
+        Win<OffT> win[kUnroll];
+        int32_t xs[kUnroll];
+#pragma unroll
+        for (int q = 0; q < kUnroll; ++q) {
+            next_win(win[q]);
+            xs[q] = load_win(win[q]);
+        }
+        int cur_j = 0;       // tail whose hits accumulate in cur_c (windows come in tail order)
+        uint32_t cur_c = 0;  // scalar
+        uint32_t vsum = 0;   // scalar: hits of this wave for t(v)
+        while (win[0].j >= 0) {
+#pragma unroll
+            for (int q = 0; q < kUnroll; ++q) {
+                const Win<OffT> w = win[q];
+                const int32_t x = xs[q];
+                next_win(win[q]);
+                xs[q] = load_win(win[q]);
+                if (w.j >= 0) {
+                    const bool val = w.base + lane < w.len;
+                    const bool hit = probe_one<MODE>(tb, x, val);
+                    const unsigned long long H = __ballot(hit);
+                    if (w.j != cur_j) {
+                        mine = (lane == cur_j) ? mine + cur_c : mine;
+                        cur_j = w.j;
+                        cur_c = 0;
+                    }
+                    if (H) {
+                        const uint32_t c = (uint32_t)__popcll(H);
+                        cur_c += c;
+                        vsum += c;
+                    }
+                }
+            }
+        }
+        mine = (lane == cur_j) ? mine + cur_c : mine;
+        local += (lane == 0) ? vsum : 0u;
+        if (ok && mine) atomicAdd(&a.t[u], (unsigned long long)mine);
+    }
+}
+
+// Bytes of the bitmap layout for `words` bitmap words and dv counters.
+__device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
+    return ((6u * words + 3u) & ~3u) + 4u * (uint32_t)dv;
+}
+
+// One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
+// wig = wave index in the group) with an LDS region of region_bytes.  The probe method is
+// chosen per vertex: the rank bitmap when it fits (AUTO or BITMAP), else the hash; or the
+// sorted list when asked for.  Returns this lane's share of t(v) in `local`.
+template <typename OffT, int PROBE, int NWAVES>
+__device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region, uint32_t region_bytes,
+                               int gtid, int wig, uint32_t& local) {
+    constexpr int gsize = NWAVES * kWave;
+    const OffT b0 = a.out_off[v];
+    const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
+    const int32_t* nv = a.adj + b0;
+
+    Table tb;
+    tb.base = v + 1;
+    int mode;
+    if constexpr (PROBE == TC_LCC_PROBE_SORTED) {
+        mode = TC_LCC_PROBE_SORTED;
+    } else {
+        tb.span = (uint32_t)(nv[dv - 1] - v);
+        tb.words = (tb.span + 31u) >> 5;
+        mode = (PROBE != TC_LCC_PROBE_HASH && bitmap_bytes(tb.words, dv) <= region_bytes) ? TC_LCC_PROBE_BITMAP
+                                                                                           : TC_LCC_PROBE_HASH;
+    }
+
+    // ---- stage N+(v)
+    if (mode == TC_LCC_PROBE_BITMAP) {
+        tb.bm = (uint32_t*)region;
+        tb.first = (uint16_t*)(tb.bm + tb.words);
+        tb.cnt = (uint32_t*)(region + ((6u * tb.words + 3u) & ~3u));
+        for (uint32_t s = gtid; s < tb.words; s += gsize) tb.bm[s] = 0u;
+        for (int j = gtid; j < dv; j += gsize) tb.cnt[j] = 0u;
+        group_sync<NWAVES>();
+        for (int j = gtid; j < dv; j += gsize) {
+            const uint32_t i = (uint32_t)(nv[j] - tb.base);
+            atomicOr(&tb.bm[i >> 5], 1u << (i & 31u));
+            if (j == 0 || ((uint32_t)(nv[j - 1] - tb.base) >> 5) != (i >> 5)) tb.first[i >> 5] = (uint16_t)j;
+        }
+    } else if (mode == TC_LCC_PROBE_HASH) {
+        int32_t T = 64;
+        while (T < 2 * dv) T <<= 1;
+        const uint32_t nb = (uint32_t)T >> 2;
+        tb.T = T;
+        tb.nb_mask = nb - 1;
+        tb.logNB = 31 - __clz(nb);
+        tb.keys = (int32_t*)region;
+        tb.cnt = (uint32_t*)(tb.keys + T);
+        for (int s = gtid; s < T; s += gsize) {
+            tb.keys[s] = -1;
+            tb.cnt[s] = 0;
+        }
+        group_sync<NWAVES>();
+        for (int j = gtid; j < dv; j += gsize) hash_insert(tb.keys, tb.nb_mask, tb.logNB, nv[j]);
+    } else {
+        tb.T = dv;
+        tb.keys = (int32_t*)region;
+        tb.cnt = (uint32_t*)(tb.keys + dv);
+        for (int j = gtid; j < dv; j += gsize) {
+            tb.keys[j] = nv[j];
+            tb.cnt[j] = 0;
+        }
+    }
+    group_sync<NWAVES>();
+
+    // ---- probe the tails of the in-edges
+    if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, v, tb, wig, local);
+    else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, v, tb, wig, local);
+    else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, v, tb, wig, local);
+    group_sync<NWAVES>();
+
+    // ---- flush the per-entry counters of N+(v)
+    if (mode == TC_LCC_PROBE_HASH) {
+        for (int s = gtid; s < tb.T; s += gsize) {
+            const uint32_t c = tb.cnt[s];
+            if (c) atomicAdd(&a.t[tb.keys[s]], (unsigned long long)c);
+        }
+    } else {
+        for (int j = gtid; j < dv; j += gsize) {
+            const uint32_t c = tb.cnt[j];
+            if (c) atomicAdd(&a.t[nv[j]], (unsigned long long)c);
+        }
+    }
+    group_sync<NWAVES>();
+}
+
+}  // namespace tcl

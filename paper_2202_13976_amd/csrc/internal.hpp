@@ -75,6 +75,7 @@ struct GraphDev {
     int64_t max_deg = 0;
     uint64_t wedges = 0;
     uint64_t staged = 0;        // sum of |N+(v)| over vertices with work
+    uint64_t push_words = 0;    // sum over oriented edges (u -> v) of |N+(v)|
     uint64_t device_bytes = 0;
     // profiling events: 0..5 build phase boundaries, 6..9 run phase boundaries
     hipEvent_t ev[10] = {};

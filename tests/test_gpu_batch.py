@@ -1,0 +1,120 @@
+"""Batched path: many graphs in one persistent launch give exactly the single-graph results."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2202_13976_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    import gc
+    gc.collect()
+    c.close()
+
+
+def build(ctx, n, s, d, ob):
+    return ctx.build_csr(n, torch.from_numpy(np.ascontiguousarray(s, np.int32)).cuda(),
+                         torch.from_numpy(np.ascontiguousarray(d, np.int32)).cuda(), offset_bytes=ob)
+
+
+def outputs(graphs):
+    tris = [torch.full((g.n,), -1, dtype=torch.int64, device="cuda") for g in graphs]
+    lccs = [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for g in graphs]
+    return tris, lccs
+
+
+def small_specs(k, seed):
+    specs = synth.batch_specs(count=k, seed=seed)
+    return [(kind, min(n, 3000), m_gen if n <= 3000 else m_gen * 3000 // n, sd) for kind, n, m_gen, sd in specs]
+
+
+def test_batch_matches_oracle(ctx):
+    print("[gpu] batch of 48 mixed graphs", flush=True)
+    specs = small_specs(48, 7)
+    raw = [synth.make(sp) for sp in specs]
+    graphs = [build(ctx, n, s, d, 4) for n, s, d in raw]
+    tris, lccs = outputs(graphs)
+    tk = ctx.batch_submit(graphs, tris, lccs)
+    done, ndone = ctx.batch_poll(tk, block=True)
+    assert done and ndone == len(graphs)
+    for (n, s, d), tri, lcc in zip(raw, tris, lccs):
+        t_ref, l_ref = oracle.tc_lcc(n, s, d)
+        np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
+        assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
+    for g in graphs:
+        g.free()
+
+
+def test_batch_mixed_widths_and_global_path(ctx):
+    """4- and 8-byte offsets in one batch, plus a clique whose out-lists exceed the LDS table."""
+    print("[gpu] batch mixed widths + K2200", flush=True)
+    raw = [synth.rmat_scale(11, 16, seed=s) for s in (1, 2, 3)] + [(5000, *synth.er(5000, 40000, seed=4))]
+    widths = [4, 8, 4, 8]
+    pairs = list(itertools.combinations(range(2200), 2))
+    a = np.array(pairs, dtype=np.int32)
+    raw.append((2200, a[:, 0].copy(), a[:, 1].copy()))
+    widths.append(8)
+    graphs = [build(ctx, n, s, d, ob) for (n, s, d), ob in zip(raw, widths)]
+    tris, lccs = outputs(graphs)
+    tk = ctx.batch_submit(graphs, tris, lccs)
+    assert ctx.batch_poll(tk, block=True)[0]
+    for (n, s, d), tri, lcc in zip(raw, tris, lccs):
+        t_ref, l_ref = oracle.tc_lcc(n, s, d)
+        np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
+        assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
+    for g in graphs:
+        g.free()
+
+
+def test_batch_equals_single_runs_and_repeats(ctx):
+    print("[gpu] batch vs single runs, repeated and overlapping tickets", flush=True)
+    specs = small_specs(40, 11)
+    raw = [synth.make(sp) for sp in specs]
+    graphs = [build(ctx, n, s, d, 4) for n, s, d in raw]
+    single = []
+    for g in graphs:
+        tri, lcc = g.run()
+        single.append((tri, lcc))
+    torch.cuda.synchronize()
+    # six overlapping submissions (more than the slots), polled afterwards in reverse order
+    subs = []
+    for i in range(6):
+        sel = graphs[i::2] if i % 2 else graphs
+        tris, lccs = outputs(sel)
+        subs.append((sel, tris, lccs, ctx.batch_submit(sel, tris, lccs)))
+    for sel, tris, lccs, tk in reversed(subs):
+        done, ndone = ctx.batch_poll(tk, block=True)
+        assert done and ndone == len(sel)
+        for g, tri, lcc in zip(sel, tris, lccs):
+            k = graphs.index(g)
+            assert torch.equal(tri, single[k][0])
+            assert lcc.cpu().numpy().tobytes() == single[k][1].cpu().numpy().tobytes()
+    for g in graphs:
+        g.free()
+
+
+def test_batch_errors(ctx):
+    n, s, d = synth.rmat_scale(9, 8, seed=3)
+    g = build(ctx, n, s, d, 4)
+    with pytest.raises(pkg.TcLccError) as e:
+        ctx.batch_poll(987654321)
+    assert e.value.status == pkg.INVALID_ARGUMENT
+    tris, lccs = outputs([g])
+    tk = ctx.batch_submit([g], tris, lccs)
+    with pytest.raises(pkg.TcLccError) as e:
+        g.free()  # still referenced by an unpolled ticket
+    assert e.value.status == pkg.BUSY
+    assert ctx.batch_poll(tk, block=True)[0]
+    g.free()

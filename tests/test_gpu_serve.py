@@ -1,0 +1,106 @@
+"""Serving loop: requests admitted by HBM budget and batched as they arrive give exactly the
+results of each graph counted alone."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2202_13976_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    import gc
+    gc.collect()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def pool(ctx):
+    specs = synth.serving_specs(count=10, seed=9, lo_scale=8, hi_scale=14)
+    graphs, alone = [], []
+    for spec in specs:
+        n, s, d = synth.make(spec)
+        g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+        tri, lcc = g.run()
+        graphs.append(g)
+        alone.append((tri, lcc))
+    torch.cuda.synchronize()
+    yield graphs, alone
+    for g in graphs:
+        g.free()
+
+
+def drive(server, graphs, picks, gaps):
+    outs, ids = [], []
+    for k, gap in zip(picks, gaps):
+        time.sleep(gap)
+        g = graphs[k]
+        tri = torch.full((g.n,), -1, dtype=torch.int64, device="cuda")
+        lcc = torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda")
+        outs.append((k, tri, lcc))
+        ids.append(server.submit(g, tri, lcc))
+    infos = [server.poll(i, block=True) for i in ids]
+    return outs, infos
+
+
+def check(outs, alone):
+    for k, tri, lcc in outs:
+        assert torch.equal(tri, alone[k][0])
+        assert lcc.cpu().numpy().tobytes() == alone[k][1].cpu().numpy().tobytes()
+
+
+@pytest.mark.parametrize("inflight,batch", [(2, 4096), (4, 8), (1, 1)])
+def test_mix_equals_alone(ctx, pool, inflight, batch):
+    print(f"[gpu] server inflight={inflight} max_batch={batch}", flush=True)
+    graphs, alone = pool
+    rng = np.random.default_rng(3)
+    picks = rng.integers(0, len(graphs), 80)
+    gaps = rng.exponential(0.0002, 80)
+    server = pkg.Server(ctx, budget_bytes=0, max_inflight=inflight, max_batch=batch)
+    outs, infos = drive(server, graphs, picks, gaps)
+    server.close()
+    check(outs, alone)
+    for inf in infos:
+        assert inf.arrival_ns <= inf.admit_ns <= inf.done_ns
+        assert 1 <= inf.batch_size <= batch
+    if batch > 1:
+        assert max(inf.batch_size for inf in infos) > 1, "arrivals during running batches must be batched"
+
+
+def test_tiny_budget_queues(ctx, pool):
+    """A budget that holds one request at a time: everything still completes, in order."""
+    graphs, alone = pool
+    budget = max(8 * g.n for g in graphs)
+    server = pkg.Server(ctx, budget_bytes=budget, max_inflight=4, max_batch=4096)
+    picks = list(range(len(graphs))) * 3
+    outs, infos = drive(server, graphs, picks, [0.0] * len(picks))
+    server.close()
+    check(outs, alone)
+    sizes = [8 * graphs[k].n for k in picks]
+    # no launch ever held more than the budget
+    for inf, sz in zip(infos, sizes):
+        assert inf.batch_size * min(sizes) <= budget + 1 or inf.batch_size == 1
+
+
+def test_over_budget_and_unknown(ctx, pool):
+    graphs, _ = pool
+    big = max(graphs, key=lambda g: g.n)
+    server = pkg.Server(ctx, budget_bytes=8 * big.n - 8, max_inflight=2)
+    tri = torch.empty(big.n, dtype=torch.int64, device="cuda")
+    with pytest.raises(pkg.TcLccError) as e:
+        server.submit(big, tri)
+    assert e.value.status == pkg.OVER_BUDGET
+    with pytest.raises(pkg.TcLccError) as e:
+        server.poll(424242)
+    assert e.value.status == pkg.INVALID_ARGUMENT
+    server.close()
