@@ -59,17 +59,27 @@ def survey_bytes(info) -> int:
     return 4 * int(info.push_words) + (4 + 2 * w) * int(info.m) + (2 * w + 16) * int(info.n)
 
 
-def stored_traffic(kernel_src: str):
+COUNT_SOURCES = ("count.hip", "count_device.hpp", "common.hpp", "internal.hpp")
+
+
+def count_source_sha() -> str:
+    """SHA-256 over the sources that define the count kernel, in a fixed order."""
+    h = hashlib.sha256()
+    for name in COUNT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2202_13976_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
     """HBM bytes per count launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; otherwise None."""
+    taken on the current kernel sources; otherwise None."""
     path = os.path.join(ROOT, "profiles", "count_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(kernel_src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != count_source_sha():
         return None
     return rec.get("bytes_per_launch")
 
@@ -146,7 +156,53 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
             "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same)}
 
 
-def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: float = 0.7):
+def run_timing(ctx, torch, n, src, dst, offset_bytes, tri, lcc, warm: int = 3, lo: int = 10, hi: int = 200):
+    """tc_lcc_run alone on a resident graph, on HIP events of the launch stream: warm up, then
+    repeat until the 95% interval of the median is within 5% of it (10 to 200 repeats)."""
+    import numpy as np
+    g = ctx.build_csr(n, src, dst, offset_bytes=offset_bytes)
+    m = int(g.info().m)
+    for _ in range(warm):
+        g.run(tri, lcc)
+    st = torch.cuda.current_stream()
+    times = []
+    while len(times) < hi:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        g.run(tri, lcc, stream=st)
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+        if len(times) >= lo:
+            a = np.array(times)
+            half = 1.96 * 1.2533 * a.std(ddof=1) / np.sqrt(len(a))  # normal approximation for the median
+            if half <= 0.05 * np.median(a):
+                break
+    g.free()
+    a = np.array(times)
+    med = float(np.median(a))
+    return {"median_ms": med, "p99_ms": float(np.percentile(a, 99)), "repeats": len(times),
+            "teps": m / (med * 1e-3)}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+SERVE_INFLIGHT = 2
+
+
+def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: float = 0.7,
+                sweep=(0.5, 0.9, 1.2), sweep_req: int = 1000, sweep_warm: int = 100):
     """Poisson request stream over a pool of resident R-MAT graphs: plain server (one request
     per launch) against the continuous-batching server, same arrivals, same GPU."""
     import numpy as np
@@ -162,9 +218,10 @@ def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: 
         graphs.append(g)
         ms.append(int(g.info().m))
         outs.append((torch.empty(n, dtype=torch.int64, device=dev), torch.empty(n, dtype=torch.float64, device=dev)))
-    picks = synth.choices(n_warm + n_req, len(graphs), seed=13)
+    picks_all = synth.choices(n_warm + n_req, len(graphs), seed=13)
 
-    def run(server, rate):
+    def run(server, rate, n_req=n_req, n_warm=n_warm):
+        picks = picks_all[:n_warm + n_req]
         gaps = synth.poisson_gaps(n_warm + n_req, rate, seed=11) if rate else np.zeros(n_warm + n_req)
         ids = []
         t0 = time.perf_counter()
@@ -188,7 +245,7 @@ def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: 
     plain = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=1)
     sat = run(plain, 0.0)
     plain.close()
-    t_edges = sum(ms[k] for k in picks[n_warm:])
+    t_edges = sum(ms[k] for k in picks_all[n_warm:])
     sat_rate = n_req * sat["teps"] / t_edges  # requests per second when the plain path is saturated
     rate = load * sat_rate
     log_fn(f"[bench] plain saturation {sat_rate:.0f} req/s; offered load {rate:.0f} req/s")
@@ -197,10 +254,18 @@ def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: 
            "plain_saturation_rps": sat_rate, "offered_rps": rate, "load": load}
     plain = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=1)
     res["plain"] = run(plain, rate)
-    plain.close()
-    batched = pkg.Server(ctx, budget_bytes=8 << 30, max_inflight=2, max_batch=4096)
+    batched = pkg.Server(ctx, budget_bytes=8 << 30, max_inflight=SERVE_INFLIGHT, max_batch=4096)
     res["batched"] = run(batched, rate)
     res["batched_saturated"] = run(batched, 0.0)
+    res["batched_inflight"] = SERVE_INFLIGHT
+    res["sweep"] = []
+    for x in sweep:
+        log_fn(f"[bench] serving sweep at {x} x plain saturation")
+        r = x * sat_rate
+        res["sweep"].append({"load": x, "offered_rps": r,
+                             "plain": run(plain, r, sweep_req, sweep_warm),
+                             "batched": run(batched, r, sweep_req, sweep_warm)})
+    plain.close()
     batched.close()
     for g in graphs:
         g.free()
@@ -218,7 +283,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="after timing, copy 1 GiB device to device 3 times (reference for HBM counters)")
+                    help="after timing, copy 1 GiB with an elementwise kernel 3 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -268,7 +333,10 @@ def main():
     run_ms = phases["run_zero_ms"] + count_ms + phases["run_epilogue_ms"]
     alg = count_bytes(info)
     achieved = alg / (count_ms * 1e-3) / 1e9
-    traffic = stored_traffic(os.path.join(ROOT, "paper_2202_13976_amd", "csrc", "count.hip"))
+    traffic = stored_traffic()
+    ctx.set_profiling(False)
+    log("[bench] tc_lcc_run on the resident graph")
+    run_res = run_timing(ctx, torch, n, src, dst, w["offset_bytes"], tri, lcc)
 
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
@@ -284,6 +352,7 @@ def main():
         "run_only_teps": m / (run_ms * 1e-3),
         "survey_alg_frac": survey_bytes(info) / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
+        "run_resident": run_res,
         "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
                   "active_vertices": int(info.active_vertices), "block_vertices": int(info.block_vertices),
                   "staged_entries": int(info.staged_entries), "max_out_degree": int(info.max_out_degree),
@@ -299,16 +368,19 @@ def main():
         out["serve"] = serve_bench(ctx, torch, log)
     ctx.close()
     if args.calibrate_copy:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a plain copy through the
+        # shader cores; copy_ itself may use the DMA engines, which the counters do not see)
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1, out=b)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = a.numel() * 4
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cb = cpu_baseline(n, s, d, args.cpu_seconds)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(out), flush=True)
 
 

@@ -147,6 +147,16 @@ tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph*
  * OK releases the ticket; INVALID_ARGUMENT for an unknown ticket. */
 tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int* graphs_done);
 
+/* Per-graph completion of a ticket that has not been released by batch_poll.
+ * done: host array of count bytes (count = the graphs of the submission); done[i]
+ * becomes 1 once graph i's outputs are written, which work issued afterwards on any
+ * stream of the device observes.  Graphs counted together in the persistent launch
+ * finish together; graphs that take the single-graph launches (id ranges whose
+ * tables do not fit LDS) run after it, least work first, and each finishes on its
+ * own.  Does not wait and does not release the ticket.  INVALID_ARGUMENT for an
+ * unknown ticket or a count that differs from the submission's. */
+tc_lcc_status tc_lcc_batch_progress(tc_lcc_ctx ctx, tc_lcc_ticket t, int count, uint8_t* done);
+
 /* ------------------------------------------------------------------ serving */
 
 /* A request server over device-resident graphs with continuous batching.
@@ -155,6 +165,8 @@ tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int*
  * hbm_budget_bytes (0 = no cap), gathers everything admitted at once into one batched
  * launch, and starts it as soon as fewer than max_inflight batches are running; so
  * requests that arrive while others run are batched together and overlap with them.
+ * Each request completes, and returns its budget share, as soon as its own graph is
+ * done (tc_lcc_batch_progress), not when its whole batch is.
  * max_inflight = max_batch = 1 gives the plain path: one request at a time through
  * tc_lcc_run.  Results are identical to tc_lcc_run's for every request. */
 typedef struct tc_lcc_server_s* tc_lcc_server;
@@ -162,7 +174,7 @@ typedef struct tc_lcc_server_s* tc_lcc_server;
 typedef struct {
     int64_t arrival_ns; /* submit time, steady clock */
     int64_t admit_ns;   /* time the request joined a launch */
-    int64_t done_ns;    /* time its launch was seen complete */
+    int64_t done_ns;    /* time its outputs were seen complete */
     int32_t batch_size; /* requests in that launch */
     int32_t status;     /* tc_lcc_status of the request */
 } tc_lcc_request_info;

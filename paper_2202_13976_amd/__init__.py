@@ -10,6 +10,7 @@ Entry points mirror include/tc_lcc.h:
     Context.build_csr(n, src, dst)     tc_lcc_build_csr     -> Graph
     Graph.run(tri, lcc, stream)        tc_lcc_run
     Context.batch_submit / batch_poll  tc_lcc_batch_submit / poll
+    Context.batch_progress             tc_lcc_batch_progress
 """
 from __future__ import annotations
 
@@ -66,6 +67,7 @@ _lib = None
 EXPORTS = [
     "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_build_csr", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
+    "tc_lcc_batch_progress",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
     "tc_lcc_server_create", "tc_lcc_server_submit", "tc_lcc_server_poll", "tc_lcc_server_destroy",
     "tc_lcc_status_string", "tc_lcc_last_error",
@@ -92,6 +94,7 @@ def lib():
     L.tc_lcc_run.argtypes = [vp, vp, vp, vp]
     L.tc_lcc_batch_submit.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(u64)]
     L.tc_lcc_batch_poll.argtypes = [vp, u64, i32, ctypes.POINTER(i32)]
+    L.tc_lcc_batch_progress.argtypes = [vp, u64, i32, ctypes.POINTER(ctypes.c_uint8)]
     L.tc_lcc_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.tc_lcc_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.tc_lcc_set_profiling.argtypes = [vp, i32]
@@ -255,6 +258,12 @@ class Context:
             return False, int(done.value)
         _check(s, "tc_lcc_batch_poll")
         return True, int(done.value)
+
+    def batch_progress(self, ticket: int, count: int):
+        """Per-graph completion flags (list of bool, submission order) of an unreleased ticket."""
+        flags = (ctypes.c_uint8 * max(count, 1))()
+        _check(lib().tc_lcc_batch_progress(self.handle, ticket, count, flags), "tc_lcc_batch_progress")
+        return [bool(flags[i]) for i in range(count)]
 
     def close(self):
         if self.handle:

@@ -38,6 +38,8 @@ struct BatchGraph {
     int64_t n;
     int64_t items;      // active vertices of the graph
     int64_t item_base;  // first item of the graph in the batch
+    int32_t index;      // position of the graph in the submission (its done flag)
+    int32_t pad_;
 };
 
 struct BatchHeader {
@@ -100,10 +102,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
             a.ctr = nullptr;
             a.slots = 0;
             const int32_t v = G.vlist[item - G.item_base];
-            uint32_t local = 0;
+            unsigned long long local = 0;
             process_vertex<OffT, TC_LCC_PROBE_AUTO, 1>(a, v, region, rb, lane, 0, local);
-            const uint32_t ws = wave_sum(local);
-            if (lane == 0 && ws) atomicAdd(&G.t[v], (unsigned long long)ws);
+            const unsigned long long ws = wave_sum(local);
+            if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
         }
     }
 }
@@ -129,8 +131,16 @@ __global__ void k_batch_epilogue(const BatchGraph* __restrict__ gs, const BatchH
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence_system();
-            done[g] = seq;
+            done[G.index] = seq;
         }
+    }
+}
+
+// Done flag of a graph that ran through the single-graph launches on this stream.
+__global__ void k_batch_mark(unsigned int* __restrict__ done, int index, unsigned int seq) {
+    if (threadIdx.x == 0) {
+        __threadfence_system();
+        done[index] = seq;
     }
 }
 
@@ -179,9 +189,25 @@ void drop_execs(Slot& s) {
     s.execs.clear();
 }
 
-tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t scratch) {
+tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t flags, size_t scratch) {
     Pool* pool = ctx->pool.get();
     bool changed = false;
+    if (flags > s.cap_done) {
+        const size_t cap = std::max<size_t>(flags, 2 * s.cap_done);
+        if (s.h_done) (void)hipHostFree(s.h_done);
+        s.h_done = nullptr;
+        if (hipHostMalloc((void**)&s.h_done, cap * sizeof(unsigned int), hipHostMallocMapped) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&s.d_done, s.h_done, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            s.h_done = nullptr;
+            s.cap_done = 0;
+            set_error("batch: mapped host allocation failed");
+            return TC_LCC_OUT_OF_MEMORY;
+        }
+        memset(s.h_done, 0, cap * sizeof(unsigned int));
+        s.cap_done = cap;
+        changed = true;
+    }
     if (graphs > s.cap_graphs) {
         size_t cap = std::max<size_t>(graphs, 2 * s.cap_graphs);
         if (s.d_graphs) pool->release(s.d_graphs);
@@ -196,17 +222,7 @@ tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t scr
             set_error("batch: pinned host allocation failed");
             return TC_LCC_OUT_OF_MEMORY;
         }
-        if (s.h_done) (void)hipHostFree(s.h_done);
-        s.h_done = nullptr;
-        if (hipHostMalloc((void**)&s.h_done, cap * sizeof(unsigned int), hipHostMallocMapped) != hipSuccess ||
-            hipHostGetDevicePointer((void**)&s.d_done, s.h_done, 0) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("batch: mapped host allocation failed");
-            return TC_LCC_OUT_OF_MEMORY;
-        }
-        memset(s.h_done, 0, cap * sizeof(unsigned int));
         s.cap_graphs = cap;
-        s.cap_done = cap;
         changed = true;
     }
     if (!s.d_hdr) {
@@ -238,7 +254,7 @@ tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t scr
 // fits, else the bucket hash for the largest out-list.
 uint32_t region_need(const GraphDev& d) {
     const uint32_t words = (uint32_t)((d.n + 31) / 32);
-    const uint32_t bm = ((6u * words + 3u) & ~3u) + 4u * (uint32_t)d.max_dplus;
+    const uint32_t bm = bitmap_bytes(words, d.max_dplus);
     int32_t T = 64;
     while (T < 2 * d.max_dplus) T <<= 1;
     const uint32_t hs = 8u * (uint32_t)T;
@@ -373,8 +389,12 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
             region = c;
             break;
         }
+    // the single-graph launches run after the batched kernel, smallest graph first, so
+    // the earliest done flags come as soon as possible
+    std::stable_sort(solo.begin(), solo.end(), [&](int a, int b) { return graphs[a]->d.wedges < graphs[b]->d.wedges; });
     const int nb = (int)(ord4.size() + ord8.size());
-    tc_lcc_status st = ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), std::max<size_t>(scratch, 1));
+    tc_lcc_status st =
+        ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), (size_t)count, std::max<size_t>(scratch, 1));
     if (st != TC_LCC_OK) return st;
 
     const uint32_t seq = e->next_seq++;
@@ -400,6 +420,8 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
             b.n = d.n;
             b.items = d.n_block + d.n_wave;
             b.item_base = item;
+            b.index = i;
+            b.pad_ = 0;
             item += b.items;
             soff += (size_t)d.n;
         }
@@ -428,6 +450,8 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         st = tc_lcc_run(graphs[i], tri[i], lcc ? lcc[i] : nullptr, s->stream);
         lk.lock();
         if (st != TC_LCC_OK) return st;
+        k_batch_mark<<<1, 64, 0, s->stream>>>(s->d_done, i, seq);
+        TCL_HIP(hipGetLastError());
     }
     TCL_HIP(hipEventRecord(s->ev, s->stream));
     s->busy = true;
@@ -481,5 +505,38 @@ extern "C" tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int 
         return TC_LCC_OK;
     }
     set_error("tc_lcc_batch_poll: unknown ticket %llu", (unsigned long long)t);
+    return TC_LCC_INVALID_ARGUMENT;
+}
+
+extern "C" tc_lcc_status tc_lcc_batch_progress(tc_lcc_ctx ctx, tc_lcc_ticket t, int count, uint8_t* done) {
+    if (!ctx || count < 0 || (count > 0 && !done)) {
+        set_error("tc_lcc_batch_progress: null argument or negative count");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (!ctx->batch) {
+        set_error("tc_lcc_batch_progress: unknown ticket %llu", (unsigned long long)t);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    Engine* e = (Engine*)ctx->batch;
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto done_it = e->completed.find(t);
+    if (done_it != e->completed.end()) {
+        if (count != done_it->second) {
+            set_error("tc_lcc_batch_progress: ticket has %d graphs, not %d", done_it->second, count);
+            return TC_LCC_INVALID_ARGUMENT;
+        }
+        memset(done, 1, (size_t)count);
+        return TC_LCC_OK;
+    }
+    for (Slot& s : e->slots) {
+        if (!s.busy || s.ticket != t) continue;
+        if (count != s.count) {
+            set_error("tc_lcc_batch_progress: ticket has %d graphs, not %d", s.count, count);
+            return TC_LCC_INVALID_ARGUMENT;
+        }
+        for (int i = 0; i < count; ++i) done[i] = __atomic_load_n(&s.h_done[i], __ATOMIC_ACQUIRE) == s.seq;
+        return TC_LCC_OK;
+    }
+    set_error("tc_lcc_batch_progress: unknown ticket %llu", (unsigned long long)t);
     return TC_LCC_INVALID_ARGUMENT;
 }

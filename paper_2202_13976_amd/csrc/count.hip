@@ -40,10 +40,10 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
         __syncthreads();
         if (it >= a.n_block) break;
         const int32_t v = a.vlist[it];
-        uint32_t local = 0;
+        unsigned long long local = 0;
         process_vertex<OffT, PROBE, kWavesPerBlock>(a, v, lds, block_bytes, threadIdx.x, w, local);
-        const uint32_t ws = wave_sum(local);
-        if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
+        const unsigned long long ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
     }
     // phase 2: light vertices, one wave each with its own slice of the LDS
     uint8_t* wregion = lds + (size_t)w * wave_bytes;
@@ -53,10 +53,10 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
         it = __shfl(it, 0, kWave);
         if ((int64_t)it >= a.n_wave) break;
         const int32_t v = a.vlist[a.n_block + it];
-        uint32_t local = 0;
+        unsigned long long local = 0;
         process_vertex<OffT, PROBE, 1>(a, v, wregion, wave_bytes, lane, 0, local);
-        const uint32_t ws = wave_sum(local);
-        if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
+        const unsigned long long ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
     }
 }
 
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
         const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
         const int32_t* nv = a.adj + b0;
         const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
-        uint32_t local = 0;
+        unsigned long long local = 0;
         for (OffT cb = i0 + (OffT)w * kWave; cb < i1; cb += (OffT)4 * kWave) {
             const OffT k = cb + lane;
             const bool ok = k < i1;
@@ -102,8 +102,8 @@ __global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
             if (hits) atomicAdd(&a.t[u], (unsigned long long)hits);
             local += hits;
         }
-        const uint32_t ws = wave_sum(local);
-        if (lane == 0 && ws) atomicAdd(&a.t[v], (unsigned long long)ws);
+        const unsigned long long ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
     }
 }
 

@@ -93,8 +93,9 @@ struct Win {
 // LDS view of the staged N+(v) for one probe method.
 //   hash:   keys[T] (-1 = empty) and cnt[T], 4-slot buckets
 //   sorted: keys[dv] = N+(v) and cnt[dv], binary search
-//   bitmap: bm[words] over ranks (v, vmax], first[words] = index in N+(v) of the first
-//           entry in each word, cnt[dv]; the entry index of a hit is first + popcount
+//   bitmap: bm[words] over ranks (v, vmax] plus one zero guard word, first[words] = index
+//           in N+(v) of the first entry in each word, cnt[dv]; the entry index of a hit is
+//           first + popcount.  Candidates outside the range clamp onto the guard word.
 struct Table {
     int32_t* keys;
     uint32_t* cnt;
@@ -108,20 +109,12 @@ struct Table {
     uint32_t words;
 };
 
+// One candidate x against the hash or sorted table (the bitmap probe is inlined in the
+// tail walk); counts the hit at its entry.
 template <int MODE>
 __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) {
     bool hit = false;
-    if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
-        const uint32_t i = (uint32_t)(x - tb.base);  // candidates are ranks above v
-        const uint32_t wi = min(i >> 5, tb.words - 1u);
-        const uint32_t word = tb.bm[wi];
-        const uint32_t bit = i & 31u;
-        hit = val && i < tb.span && ((word >> bit) & 1u);
-        if (hit) {
-            const uint32_t pos = (uint32_t)tb.first[wi] + (uint32_t)__popc(word & ((1u << bit) - 1u));
-            atomicAdd(&tb.cnt[pos], 1u);
-        }
-    } else if constexpr (MODE == TC_LCC_PROBE_HASH) {
+    if constexpr (MODE == TC_LCC_PROBE_HASH) {
         // bucket chain from the home bucket; each matching key bumps its own counter (the
         // slot is the bucket address plus an immediate offset)
         uint32_t b = hash32(x) >> (32 - tb.logNB);
@@ -161,8 +154,18 @@ __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) 
 }
 
 // Each wave walks the tails of its chunks of 64 in-edges of v and probes every candidate.
+//
+// Windows of 64 consecutive candidates of one tail come from a generator whose state is
+// wave-uniform (tail j is owned by lane j; the tail's start pointer is formed once per
+// tail), so a window costs a few scalar operations.  A ring of 2 * kUnroll windows is
+// kept in flight: the loads of one half arrive while the other half is probed.  For the
+// rank bitmap the LDS reads of all windows of a half are issued before any is used, so
+// one LDS round trip serves kUnroll windows.  Every hit found here is a triangle with v
+// as its middle vertex, so the chunk's hits are also v's share (`local`).
 template <typename OffT, int MODE, int NWAVES>
-__device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig, uint32_t& local) {
+__device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig,
+                           unsigned long long& local) {
+    constexpr int kRing = 2 * kUnroll;
     const int lane = lane_id();
     const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
     for (OffT cb = i0 + (OffT)wig * kWave; cb < i1; cb += (OffT)NWAVES * kWave) {
@@ -179,95 +182,108 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
         const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
         uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
 
-        // window generator over the chunk, all state scalar: tail gj, next base gbase
-        int gj = 0, gbase = 0;
-        OffT gst = 0;
-        int32_t glen = 0;
+        // generator: tail gj (gjv = gj while gj < nk, else -1), next window at gbase;
+        // a spent generator yields windows of tail -1 that read adj[0]
+        const int32_t* tptr = a.adj;
+        int gj = 0, gjv = -1, gbase = 0, glen = 1;
         auto fetch_tail = [&]() {
             if (gj < nk) {
                 const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st & 0xffffffffu), gj);
-                OffT s = (OffT)lo32;
-                if constexpr (sizeof(OffT) == 8) {
-                    const uint32_t hi32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st >> 32), gj);
-                    s = (OffT)(((uint64_t)hi32 << 32) | lo32);
-                }
-                gst = s;
+                uint64_t s = lo32;
+                if constexpr (sizeof(OffT) == 8)
+                    s |= (uint64_t)__builtin_amdgcn_readlane((uint32_t)((uint64_t)st >> 32), gj) << 32;
+                tptr = a.adj + s;
                 glen = __builtin_amdgcn_readlane(len, gj);
+                gjv = gj;
+            } else {
+                tptr = a.adj;
+                glen = 1;
+                gjv = -1;
             }
         };
         fetch_tail();
-        auto next_win = [&](Win<OffT>& w) {
-            if (gj >= nk) {
-                w.j = -1;
-                w.st = 0;
-                w.len = 1;
-                w.base = 0;
-                return;
-            }
-            w.st = gst;
-            w.len = glen;
-            w.base = gbase;
-            w.j = gj;
+        // next window: its tail j, the number of lanes holding candidates, and this lane's
+        // candidate (lanes past the tail re-read its last one; they are masked by `lim`)
+        auto gen = [&](int& j, int& lim) -> int32_t {
+            j = gjv;
+            lim = glen - gbase;
+            const uint32_t off = min((uint32_t)(gbase + lane), (uint32_t)(glen - 1));
+            const int32_t x = *(const int32_t*)((const char*)tptr + (off << 2));
             gbase += kWave;
             if (gbase >= glen) {
                 gbase = 0;
                 ++gj;
                 fetch_tail();
             }
-        };
-        // unconditional load (a spent generator yields adj[0]) so that the compiler can wait
-        // for the oldest window only; lanes past the tail re-read its last candidate
-        auto load_win = [&](const Win<OffT>& w) -> int32_t {
-            const int32_t* tp = a.adj + w.st;
-            const uint32_t off = (uint32_t)min(w.base + lane, w.len - 1);
-            return tp[off];
+            return x;
         };
 
-        // ring of kUnroll windows: slot q holds windows q, q + kUnroll, ...; a slot is probed
-        // and refilled in place, so each load keeps its register until it is consumed
-        Win<OffT> win[kUnroll];
-        int32_t xs[kUnroll];
+        int js[kRing], lims[kRing];
+        int32_t xs[kRing];
 #pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-            next_win(win[q]);
-            xs[q] = load_win(win[q]);
-        }
+        for (int q = 0; q < kRing; ++q) xs[q] = gen(js[q], lims[q]);
         int cur_j = 0;       // tail whose hits accumulate in cur_c (windows come in tail order)
-        uint32_t cur_c = 0;  // scalar
-        uint32_t vsum = 0;   // scalar: hits of this wave for t(v)
-        while (win[0].j >= 0) {
+        uint32_t cur_c = 0;  // wave-uniform
+        // a tail's count is written to its owner lane once, when the next tail starts (every
+        // tail has at least one window)
+        auto account = [&](int j, unsigned long long H) {
+            if (j != cur_j) {
+                // lane cur_j of `mine` := cur_c (a register write, no memory access)
+                asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(cur_c), "{m0}"(cur_j));
+                cur_j = j;
+                cur_c = 0;
+            }
+            cur_c += (uint32_t)__popcll(H);
+        };
+        while (js[0] >= 0) {
 #pragma unroll
-            for (int q = 0; q < kUnroll; ++q) {
-                const Win<OffT> w = win[q];
-                const int32_t x = xs[q];
-                next_win(win[q]);
-                xs[q] = load_win(win[q]);
-                if (w.j >= 0) {
-                    const bool val = w.base + lane < w.len;
-                    const bool hit = probe_one<MODE>(tb, x, val);
-                    const unsigned long long H = __ballot(hit);
-                    if (w.j != cur_j) {
-                        mine = (lane == cur_j) ? mine + cur_c : mine;
-                        cur_j = w.j;
-                        cur_c = 0;
+            for (int h = 0; h < 2; ++h) {
+                if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
+                    uint32_t ii[kUnroll], wd[kUnroll], fs[kUnroll];
+#pragma unroll
+                    for (int q = 0; q < kUnroll; ++q) {
+                        ii[q] = (uint32_t)(xs[h * kUnroll + q] - tb.base);  // candidates are ranks above v
+                        const uint32_t wi = min(ii[q] >> 5, tb.words);      // beyond the range: guard word
+                        wd[q] = tb.bm[wi];
+                        fs[q] = tb.first[wi];
                     }
-                    if (H) {
-                        const uint32_t c = (uint32_t)__popcll(H);
-                        cur_c += c;
-                        vsum += c;
+#pragma unroll
+                    for (int q = 0; q < kUnroll; ++q) {
+                        const int sl = h * kUnroll + q;
+                        asm volatile("" : "+v"(fs[q]));  // keep the read ahead of the hit branch
+                        if (js[sl] >= 0) {
+                            const uint32_t bit = ii[q] & 31u;
+                            const bool hit = lane < lims[sl] && ((wd[q] >> bit) & 1u);
+                            const unsigned long long H = __builtin_amdgcn_ballot_w64(hit);
+                            if (hit) atomicAdd(&tb.cnt[fs[q] + (uint32_t)__popc(wd[q] & ((1u << bit) - 1u))], 1u);
+                            account(js[sl], H);
+                        }
+                        xs[sl] = gen(js[sl], lims[sl]);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kUnroll; ++q) {
+                        const int sl = h * kUnroll + q;
+                        const int32_t x = xs[sl];
+                        const int j = js[sl], lim = lims[sl];
+                        xs[sl] = gen(js[sl], lims[sl]);
+                        if (j >= 0) {
+                            const bool hit = probe_one<MODE>(tb, x, lane < lim);
+                            account(j, __builtin_amdgcn_ballot_w64(hit));
+                        }
                     }
                 }
             }
         }
-        mine = (lane == cur_j) ? mine + cur_c : mine;
-        local += (lane == 0) ? vsum : 0u;
+        asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(cur_c), "{m0}"(cur_j));
+        local += mine;
         if (ok && mine) atomicAdd(&a.t[u], (unsigned long long)mine);
     }
 }
 
-// Bytes of the bitmap layout for `words` bitmap words and dv counters.
-__device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
-    return ((6u * words + 3u) & ~3u) + 4u * (uint32_t)dv;
+// Bytes of the bitmap layout for `words` bitmap words (plus the guard word) and dv counters.
+__host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
+    return ((6u * (words + 1u) + 3u) & ~3u) + 4u * (uint32_t)dv;
 }
 
 // One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
@@ -276,7 +292,7 @@ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
 // sorted list when asked for.  Returns this lane's share of t(v) in `local`.
 template <typename OffT, int PROBE, int NWAVES>
 __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region, uint32_t region_bytes,
-                               int gtid, int wig, uint32_t& local) {
+                               int gtid, int wig, unsigned long long& local) {
     constexpr int gsize = NWAVES * kWave;
     const OffT b0 = a.out_off[v];
     const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
@@ -297,9 +313,9 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
     // ---- stage N+(v)
     if (mode == TC_LCC_PROBE_BITMAP) {
         tb.bm = (uint32_t*)region;
-        tb.first = (uint16_t*)(tb.bm + tb.words);
-        tb.cnt = (uint32_t*)(region + ((6u * tb.words + 3u) & ~3u));
-        for (uint32_t s = gtid; s < tb.words; s += gsize) tb.bm[s] = 0u;
+        tb.first = (uint16_t*)(tb.bm + tb.words + 1);
+        tb.cnt = (uint32_t*)(region + ((6u * (tb.words + 1u) + 3u) & ~3u));
+        for (uint32_t s = gtid; s <= tb.words; s += gsize) tb.bm[s] = 0u;  // with the guard word
         for (int j = gtid; j < dv; j += gsize) tb.cnt[j] = 0u;
         group_sync<NWAVES>();
         for (int j = gtid; j < dv; j += gsize) {

@@ -6,8 +6,10 @@
 // its graph, 8 bytes per vertex), groups everything admitted at once into one batch of
 // the persistent batched launch, and starts it as soon as one of the in-flight slots is
 // free.  Requests that arrive while earlier batches run join the next batch and overlap
-// with them on the GPU.  Completion is observed by polling the batch tickets; every
-// request records its arrival, admission and completion times (steady clock, ns).
+// with them on the GPU.  Completion is observed per request from the per-graph done
+// flags of its batch, so a small graph batched with a large one leaves as soon as it is
+// counted; every request records its arrival, admission and completion times (steady
+// clock, ns).
 // With batching off the server runs one request at a time through tc_lcc_run, the
 // plain one-graph-per-launch path, for comparison.
 #include <chrono>
@@ -37,6 +39,8 @@ struct Request {
 
 struct Flight {
     std::vector<Request*> reqs;
+    std::vector<uint8_t> flags;  // per-request completion of a batch
+    int open = 0;                // requests not yet retired
     uint64_t bytes = 0;
     tc_lcc_ticket ticket = 0;  // batching
     hipEvent_t ev = nullptr;   // plain path
@@ -67,16 +71,38 @@ struct tc_lcc_server_s {
 namespace tcl {
 namespace {
 
+// Completes one request of flight f: its budget share is returned and pollers wake up.
+void retire(tc_lcc_server s, Flight& f, Request* r, int64_t t, tc_lcc_status st) {
+    r->t_done = t;
+    r->status = st;
+    r->done = true;
+    r->g->inflight--;
+    s->inflight_bytes -= r->bytes;
+    f.open--;
+    s->cv_done.notify_all();
+}
+
 void worker_loop(tc_lcc_server s) {
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // 1. retire finished flights
+        // 1. retire finished requests, and flights whose launch is over
         for (size_t i = 0; i < s->flights.size();) {
             Flight& f = s->flights[i];
             bool finished = false;
             tc_lcc_status st = TC_LCC_OK;
             if (s->batching) {
+                // requests whose graph is done leave at once; the ticket is released
+                // once the whole launch is over
+                if (f.open > 0 &&
+                    tc_lcc_batch_progress(s->ctx, f.ticket, (int)f.reqs.size(), f.flags.data()) == TC_LCC_OK) {
+                    const int64_t t = now_ns();
+                    for (size_t k = 0; k < f.reqs.size(); ++k) {
+                        Request* r = f.reqs[k];
+                        if (!f.flags[k] || r->done) continue;
+                        retire(s, f, r, t, TC_LCC_OK);
+                    }
+                }
                 st = tc_lcc_batch_poll(s->ctx, f.ticket, 0, nullptr);
                 finished = st != TC_LCC_NOT_READY;
                 if (st == TC_LCC_NOT_READY) st = TC_LCC_OK;
@@ -90,16 +116,10 @@ void worker_loop(tc_lcc_server s) {
                 continue;
             }
             const int64_t t = now_ns();
-            for (Request* r : f.reqs) {
-                r->t_done = t;
-                r->status = st;
-                r->done = true;
-                r->g->inflight--;
-            }
+            for (Request* r : f.reqs)
+                if (!r->done) retire(s, f, r, t, st);
             if (f.ev) (void)hipEventDestroy(f.ev);
-            s->inflight_bytes -= f.bytes;
             s->flights.erase(s->flights.begin() + (long)i);
-            s->cv_done.notify_all();
         }
         // 2. admit and launch while a slot is free and the budget allows
         while ((int)s->flights.size() < s->max_inflight && !s->pending.empty()) {
@@ -147,6 +167,8 @@ void worker_loop(tc_lcc_server s) {
                 continue;
             }
             s->inflight_bytes += f.bytes;
+            f.open = (int)f.reqs.size();
+            f.flags.assign(f.reqs.size(), 0);
             s->flights.push_back(std::move(f));
         }
         if (s->stop && s->pending.empty() && s->flights.empty()) break;

@@ -1,5 +1,6 @@
 """Batched path: many graphs in one persistent launch give exactly the single-graph results."""
 import itertools
+import time
 
 import numpy as np
 import pytest
@@ -118,3 +119,43 @@ def test_batch_errors(ctx):
     assert e.value.status == pkg.BUSY
     assert ctx.batch_poll(tk, block=True)[0]
     g.free()
+
+
+def test_batch_progress_per_graph(ctx):
+    """Per-graph done flags: graphs of the persistent launch finish before the ones that take
+    the single-graph launches, those finish least work first, and every flagged output is final."""
+    print("[gpu] batch progress flags", flush=True)
+    raw = [synth.rmat_scale(10, 16, seed=s) for s in (1, 2, 3)]
+    pairs = np.array(list(itertools.combinations(range(2200), 2)), dtype=np.int32)
+    raw.insert(1, (2200, pairs[:, 0].copy(), pairs[:, 1].copy()))        # beyond the LDS table
+    sub = pairs[pairs[:, 1] < 2100]
+    raw.insert(0, (2100, sub[:, 0].copy(), sub[:, 1].copy()))            # beyond it, less work
+    graphs = [build(ctx, n, s, d, 4) for n, s, d in raw]
+    single = [g.run() for g in graphs]
+    torch.cuda.synchronize()
+    tris, lccs = outputs(graphs)
+    tk = ctx.batch_submit(graphs, tris, lccs)
+    seen = [None] * len(graphs)
+    step = 0
+    t_end = time.monotonic() + 60
+    while not all(x is not None for x in seen):
+        assert time.monotonic() < t_end, "flags never came up"
+        for i, f in enumerate(ctx.batch_progress(tk, len(graphs))):
+            if f and seen[i] is None:
+                seen[i] = step
+                assert torch.equal(tris[i], single[i][0])
+        step += 1
+    with pytest.raises(pkg.TcLccError) as e:
+        ctx.batch_progress(tk, len(graphs) + 1)
+    assert e.value.status == pkg.INVALID_ARGUMENT
+    assert ctx.batch_poll(tk, block=True)[0]
+    with pytest.raises(pkg.TcLccError):
+        ctx.batch_progress(tk, len(graphs))
+    # positions: 0 = K2100, 2 = K2200 (single-graph launches); 1, 3, 4 = small R-MAT graphs
+    small = [seen[i] for i in (1, 3, 4)]
+    assert max(small) <= min(seen[0], seen[2])   # the persistent launch comes first
+    assert seen[0] <= seen[2]                   # then the single-graph launches, least work first
+    for (tri, lcc), i in zip(single, range(len(graphs))):
+        assert lccs[i].cpu().numpy().tobytes() == lcc.cpu().numpy().tobytes()
+    for g in graphs:
+        g.free()
