@@ -346,9 +346,10 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     uint32_t* scan32 = (uint32_t*)((uint8_t*)sort_scratch + rs_bytes);
     OffT* scanO = (OffT*)scan32;
     uint64_t* scan64 = (uint64_t*)scan32;
-    int* bad;
+    int* bad;  // [0]: an endpoint outside [0, n); [1]: a sort's look-back wait gave up
     TCL_TRY(tmp.get(16, &bad));
     TCL_HIP(fill<int>(bad, 16, 0, st));
+    unsigned int* sort_err = (unsigned int*)(bad + 1);
     uint32_t *f1, *l1, *f2, *l2;
     TCL_TRY(tmp.get(N, &f1));
     TCL_TRY(tmp.get(N, &l1));
@@ -365,7 +366,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     if (M > 0) {
         k_make_keys<<<grid_for(M, kB, 8192), kB, 0, st>>>(s_dev, d_dev, M, n, bits, ka, bad);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(ka, kb, M, 0, 2 * bits, sort_scratch, st, &sorted));
+        TCL_HIP(radix_sort_u64(ka, kb, M, 0, 2 * bits, sort_scratch, sort_err, st, &sorted));
         ukeys = (sorted == ka) ? kb : ka;
         TCL_HIP(exclusive_scan<uint32_t>(UniqueFlag{sorted, M, (1ull << (2 * bits)) - 1}, M + 1, pos, scan32, st));
         k_compact_unique<<<grid_for(M, kB, 8192), kB, 0, st>>>(sorted, M, bits, pos, ukeys, kc);
@@ -391,7 +392,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_HIP(run_bounds(GroupShift{ukeys, bits}, m, f1, l1, n, st));
     {
         uint64_t* hs = kc;
-        if (m > 0) TCL_HIP(radix_sort_u64(kc, spare, m, 32, bits, sort_scratch, st, &hs));
+        if (m > 0) TCL_HIP(radix_sort_u64(kc, spare, m, 32, bits, sort_scratch, sort_err, st, &hs));
         TCL_HIP(run_bounds(GroupShift{hs, 32}, m, f2, l2, n, st));
     }
     k_degrees<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, f2, l2, n, deg);
@@ -407,7 +408,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         uint64_t* rs = spare;
         k_rank_keys<<<grid_for(N, kB, 8192), kB, 0, st>>>(deg, n, bits, spare);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(spare, kc, N, 0, 2 * bits, sort_scratch, st, &rs));
+        TCL_HIP(radix_sort_u64(spare, kc, N, 0, 2 * bits, sort_scratch, sort_err, st, &rs));
         k_rank_scatter<<<grid_for(N, kB, 8192), kB, 0, st>>>(rs, n, bits, d.order, rank, d.deg_r);
         TCL_HIP(hipGetLastError());
     }
@@ -424,7 +425,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     if (m > 0) {
         k_relabel<<<grid_for(m, kB, 8192), kB, 0, st>>>(ukeys, m, bits, rank, okeys);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(okeys, kc, m, 0, 2 * bits, sort_scratch, st, &osorted));
+        TCL_HIP(radix_sort_u64(okeys, kc, m, 0, 2 * bits, sort_scratch, sort_err, st, &osorted));
     }
     TCL_HIP(run_bounds(GroupShift{osorted, bits}, m, f1, l1, n, st));
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, n, d.dplus);
@@ -461,7 +462,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     d.in_off = in_off;
     TCL_TRY(keep(g, N, &d.work));
     uint64_t* ws = wa;
-    if (kept > 0) TCL_HIP(radix_sort_u64(wa, wb, kept, 32, bits, sort_scratch, st, &ws));
+    if (kept > 0) TCL_HIP(radix_sort_u64(wa, wb, kept, 32, bits, sort_scratch, sort_err, st, &ws));
     TCL_HIP(run_bounds(GroupShift{ws, 32}, kept, f2, l2, n, st));
     int32_t* din = deg;  // degrees by vertex are not needed any more (deg_r keeps them by rank)
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f2, l2, n, din);
@@ -488,8 +489,14 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     k_stats<<<grid_for(N, kB, 2048), kB, 0, st>>>(d.dplus, d.deg_r, (const unsigned long long*)d.work, n, stats);
     TCL_HIP(hipGetLastError());
     unsigned long long hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int serr = 0;
     TCL_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipMemcpyAsync(&serr, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     TCL_HIP(hipStreamSynchronize(st));
+    if (serr) {
+        set_error("tc_lcc_build_csr: a radix sort pass gave up waiting for an earlier tile");
+        return TC_LCC_DEVICE_ERROR;
+    }
     d.max_dplus = (int32_t)hs[0];
     d.max_deg = (int64_t)hs[1];
     d.wedges = hs[2];
@@ -573,20 +580,29 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     const size_t n = (size_t)d.n;
     uint64_t *ka, *kb, *res;
     unsigned long long* counts;
+    unsigned int* sort_err;
     void* scr;
     TCL_TRY(tmp.get(std::max<size_t>(n, 1), &ka));
     TCL_TRY(tmp.get(std::max<size_t>(n, 1), &kb));
     TCL_TRY(tmp.get(64, &counts));
+    TCL_TRY(tmp.get(64, &sort_err));
     TCL_TRY(tmp.get(radix_sort_scratch_bytes(std::max<size_t>(n, 1)), (uint8_t**)&scr));
     TCL_HIP(fill<unsigned long long>(counts, 64, 0ull, st));
+    TCL_HIP(fill<unsigned int>(sort_err, 64, 0u, st));
     const int group = tn.group;
     k_classify<<<grid_for(n, kB, 4096), kB, 0, st>>>((const unsigned long long*)d.work, d.dplus, d.n, d.bits,
                                                      tn.wave_work_max, wave_cap, block_cap, group, ka, counts);
     TCL_HIP(hipGetLastError());
-    TCL_HIP(radix_sort_u64(ka, kb, n, 0, d.bits + 6, scr, st, &res));
+    TCL_HIP(radix_sort_u64(ka, kb, n, 0, d.bits + 6, scr, sort_err, st, &res));
     unsigned long long hc[64];
+    unsigned int herr = 0;
     TCL_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipMemcpyAsync(&herr, sort_err, sizeof(herr), hipMemcpyDeviceToHost, st));
     TCL_HIP(hipStreamSynchronize(st));
+    if (herr) {
+        set_error("schedule: a radix sort pass gave up waiting for an earlier tile");
+        return TC_LCC_DEVICE_ERROR;
+    }
     int64_t nb = 0;
     for (int c = 0; c < kClassWave; ++c) nb += (int64_t)hc[c];
     d.n_block = nb;
