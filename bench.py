@@ -198,7 +198,7 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
 
 
-SERVE_INFLIGHT = 2
+SERVE_INFLIGHT = 4
 
 
 def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: float = 0.7,

@@ -354,14 +354,9 @@ extern "C" tc_lcc_status tc_lcc_graph_free(tc_lcc_graph g) {
 
 // ------------------------------------------------------------------ one graph
 
-extern "C" tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, void* hip_stream) {
-    if (!g || !tri) {
-        set_error("tc_lcc_run: null graph or output");
-        return TC_LCC_INVALID_ARGUMENT;
-    }
+tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu) {
     tc_lcc_ctx ctx = g->ctx;
     TCL_HIP(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)hip_stream;
     tc_lcc_tuning tn;
     uint64_t gen;
     {
@@ -379,13 +374,21 @@ extern "C" tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, 
     mark(g->d, 6, st);
     tc_lcc_status s = launch_zero_counts(g, st);
     mark(g->d, 7, st);
-    if (s == TC_LCC_OK) s = launch_count(g, tn, st);
+    if (s == TC_LCC_OK) s = launch_count(g, tn, spare_per_cu, st);
     mark(g->d, 8, st);
     if (s == TC_LCC_OK) s = launch_epilogue(g, tri, lcc, st);
     mark(g->d, 9, st);
     if (s != TC_LCC_OK) return s;
     TCL_HIP(hipEventRecord(g->last_use, st));
     return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, void* hip_stream) {
+    if (!g || !tri) {
+        set_error("tc_lcc_run: null graph or output");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    return run_graph(g, tri, lcc, (hipStream_t)hip_stream, 0);
 }
 
 // ------------------------------------------------------------------ profiling

@@ -6,11 +6,16 @@
 // device queue a few at a time, find the item's graph by a binary search over
 // the per-graph item offsets, and count the vertex exactly as the single-graph
 // kernel does (rank bitmap of N+(v) in LDS where it fits, bucket hash otherwise).
-// Clearing the counters, counting and the LCC epilogue form one HIP graph that
+// The count grid is sized to the batch's items (a few grid classes), so a small
+// batch does not start thousands of waves that only find an empty queue.
+// The LCC epilogue runs over chunks of every graph's vertices; it resets each
+// counter to zero after reading it (so the slot's counters are clean for the next
+// batch without a clearing pass), and the block that finishes a graph's last chunk
+// raises that graph's done flag.  Counting and the epilogue form one HIP graph that
 // is captured once per launch shape and replayed for every batch: all sizes and
 // pointers are read from device memory that each submission rewrites, so the
 // capture does not depend on the batch.  Each context holds a few slots (own
-// stream, descriptors, counters and HIP graph), so batches can overlap on the GPU.
+// stream, descriptors, counters and HIP graphs), so batches can overlap on the GPU.
 #include <cstring>
 #include <set>
 
@@ -21,6 +26,7 @@ namespace tcl {
 constexpr int kBatchSlots = 4;
 constexpr int kBatchThreads = 256;
 constexpr int kBatchGrab = 8;  // items a wave takes per queue access
+constexpr int kEpiChunk = 4096;  // vertices per epilogue work item
 
 struct BatchGraph {
     const void* out_off;
@@ -36,90 +42,147 @@ struct BatchGraph {
     unsigned long long* tri;
     double* lcc;
     int64_t n;
-    int64_t items;      // active vertices of the graph
-    int64_t item_base;  // first item of the graph in the batch
+    int64_t heavy;      // its heaviest vertices (>= 2^14 probes): vlist[0, heavy), heaviest first
+    int64_t light;      // all its other active vertices: vlist[heavy, heavy + light)
+    int64_t heavy_base; // first heavy item of the graph in the batch
+    int64_t light_base; // first light item of the graph in the batch
+    int64_t chunk_base; // first epilogue chunk of the graph in the batch
     int32_t index;      // position of the graph in the submission (its done flag)
-    int32_t pad_;
+    int32_t nchunks;    // epilogue chunks of the graph
+    unsigned int chunks_done;  // epilogue chunks finished (0 in every submission)
+    uint32_t pad_;
 };
 
 struct BatchHeader {
     int32_t count;        // graphs in the batch
     int32_t count4;       // graphs [0, count4) use 4-byte offsets, the rest 8-byte ones
-    int64_t items4;       // items of the 4-byte graphs
-    int64_t items;        // all items
+    int64_t heavy4, heavy;  // heavy items of the 4-byte graphs, of all graphs
+    int64_t light4, light;  // light items likewise
     uint32_t region;      // LDS bytes per wave
     uint32_t seq;         // submission number, written to the done flags
-    unsigned int queue[2];
+    unsigned int queue[4];  // [2 * which]: heavy items, [2 * which + 1]: light grabs taken from the queue
+    int64_t chunks;       // epilogue chunks of all graphs
 };
 
-__global__ void k_batch_zero(const BatchGraph* __restrict__ gs, BatchHeader* h) {
-    if (blockIdx.x == 0 && threadIdx.x < 2) h->queue[threadIdx.x] = 0u;
-    const int count = h->count;
-    for (int g = blockIdx.x; g < count; g += gridDim.x) {
-        unsigned long long* t = gs[g].t;
-        const int64_t n = gs[g].n;
-        for (int64_t r = threadIdx.x; r < n; r += blockDim.x) t[r] = 0ull;
-    }
+template <typename OffT>
+__device__ __forceinline__ CountArgs<OffT> batch_args(const BatchGraph& G) {
+    CountArgs<OffT> a;
+    a.out_off = (const OffT*)G.out_off;
+    a.adj = G.adj;
+    a.in_off = (const OffT*)G.in_off;
+    a.in_u = G.in_u;
+    a.in_start = (const OffT*)G.in_start;
+    a.in_len = G.in_len;
+    a.vlist = G.vlist;
+    a.n_block = a.n_wave = a.n_global = 0;
+    a.t = G.t;
+    a.ctr = nullptr;
+    a.slots = 0;
+    return a;
 }
 
+// Last graph g in [g_lo, g_hi) whose items start at or before `item` (base selects the
+// heavy or the light numbering).
+template <bool HEAVY>
+__device__ __forceinline__ int batch_graph_of(const BatchGraph* __restrict__ gs, int g_lo, int g_hi, int64_t item) {
+    int ga = g_lo, gb = g_hi - 1;
+    while (ga < gb) {
+        const int mid = (ga + gb + 1) >> 1;
+        if ((HEAVY ? gs[mid].heavy_base : gs[mid].light_base) <= item) ga = mid;
+        else gb = mid - 1;
+    }
+    return ga;
+}
+
+// Two phases, as in the single-graph kernel: the heavy vertices of all graphs (those with at
+// least 2^14 probes), one block each (the block's whole LDS is the table), taken one at a
+// time; then all others, one wave each in its slice of the LDS (every vertex of a batched
+// graph fits a slice), taken kBatchGrab at a time when there are plenty.
 template <typename OffT>
 __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph* __restrict__ gs, BatchHeader* h,
                                                                int which) {
     extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int64_t s_item;
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t rb = h->region;
-    uint8_t* region = lds + (size_t)w * rb;
-    const int64_t lo = which ? h->items4 : 0, hi = which ? h->items : h->items4;
     const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
-    for (;;) {
-        unsigned int it = 0;
-        if (lane == 0) it = atomicAdd(&h->queue[which], (unsigned int)kBatchGrab);
-        it = __shfl(it, 0, kWave);
-        int64_t item = lo + (int64_t)it;
+
+    // the first item of every block and the first grab of every wave are fixed by their
+    // index; only later ones come from the queue counters (atomics on one address serialize)
+    const int64_t grid = gridDim.x;
+    const int64_t hlo = which ? h->heavy4 : 0, hhi = which ? h->heavy : h->heavy4;
+    for (int64_t item = hlo + blockIdx.x;;) {
+        if (item >= hhi) break;
+        int g = __builtin_amdgcn_readfirstlane(batch_graph_of<true>(gs, g_lo, g_hi, item));
+        while (item >= gs[g].heavy_base + gs[g].heavy) ++g;  // graphs without heavy vertices
+        const BatchGraph& G = gs[g];
+        const CountArgs<OffT> a = batch_args<OffT>(G);
+        const int32_t v = G.vlist[item - G.heavy_base];
+        unsigned long long local = 0;
+        process_vertex<OffT, TC_LCC_PROBE_AUTO, kBatchThreads / kWave>(a, v, lds, rb * (kBatchThreads / kWave),
+                                                                        threadIdx.x, w, local);
+        const unsigned long long ws = wave_sum(local);
+        if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
+        if (grid >= hhi - hlo) break;
+        if (threadIdx.x == 0) s_item = hlo + grid + (int64_t)atomicAdd(&h->queue[2 * which], 1u);
+        __syncthreads();
+        item = s_item;
+        __syncthreads();
+    }
+
+    uint8_t* region = lds + (size_t)w * rb;
+    const int64_t lo = which ? h->light4 : 0, hi = which ? h->light : h->light4;
+    const int64_t waves = grid * (kBatchThreads / kWave);
+    // light grabs: several items when there are plenty per wave, single ones when few; the
+    // fixed first grabs go to the last blocks first, which hold no heavy vertex
+    const int grab = (hi - lo) >= waves * (int64_t)kBatchGrab * 4 ? kBatchGrab : 1;
+    for (int64_t item = lo + ((grid - 1 - blockIdx.x) * (int64_t)(kBatchThreads / kWave) + w) * grab;;) {
         if (item >= hi) break;
-        const int64_t end = min(item + kBatchGrab, hi);
-        // graph of the first item: last g with item_base <= item
-        int ga = g_lo, gb = g_hi - 1;
-        while (ga < gb) {
-            const int mid = (ga + gb + 1) >> 1;
-            if (gs[mid].item_base <= item) ga = mid;
-            else gb = mid - 1;
-        }
-        int g = __builtin_amdgcn_readfirstlane(ga);
+        const int64_t end = min(item + (int64_t)grab, hi);
+        int g = __builtin_amdgcn_readfirstlane(batch_graph_of<false>(gs, g_lo, g_hi, item));
         for (; item < end; ++item) {
-            while (item >= gs[g].item_base + gs[g].items) ++g;  // graphs with no items are skipped
+            while (item >= gs[g].light_base + gs[g].light) ++g;  // graphs without light vertices
             const BatchGraph& G = gs[g];
-            CountArgs<OffT> a;
-            a.out_off = (const OffT*)G.out_off;
-            a.adj = G.adj;
-            a.in_off = (const OffT*)G.in_off;
-            a.in_u = G.in_u;
-            a.in_start = (const OffT*)G.in_start;
-            a.in_len = G.in_len;
-            a.vlist = G.vlist;
-            a.n_block = a.n_wave = a.n_global = 0;
-            a.t = G.t;
-            a.ctr = nullptr;
-            a.slots = 0;
-            const int32_t v = G.vlist[item - G.item_base];
+            const CountArgs<OffT> a = batch_args<OffT>(G);
+            const int32_t v = G.vlist[G.heavy + (item - G.light_base)];
             unsigned long long local = 0;
             process_vertex<OffT, TC_LCC_PROBE_AUTO, 1>(a, v, region, rb, lane, 0, local);
             const unsigned long long ws = wave_sum(local);
             if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
         }
+        if (waves * grab >= hi - lo) break;
+        unsigned int q = 0;
+        if (lane == 0) q = atomicAdd(&h->queue[2 * which + 1], 1u);
+        q = __shfl(q, 0, kWave);
+        item = lo + (waves + (int64_t)q) * grab;
     }
 }
 
-// Eq. 2 per vertex, as the single-graph epilogue; each graph then raises its done flag.
-__global__ void k_batch_epilogue(const BatchGraph* __restrict__ gs, const BatchHeader* h,
-                                 unsigned int* __restrict__ done) {
+// Eq. 2 per vertex, as the single-graph epilogue, over chunks of kEpiChunk vertices of all
+// graphs; each counter is reset to zero once read.  A graph's done flag goes up when its
+// last chunk is finished: every wave first waits for its own stores, the block's first
+// thread then makes them visible device-wide and counts the chunk; the thread that counts
+// the last chunk makes everything visible to the host and raises the flag.
+__global__ __launch_bounds__(256) void k_batch_epilogue(BatchGraph* __restrict__ gs, const BatchHeader* h,
+                                                        unsigned int* __restrict__ done) {
     const int count = h->count;
+    const int64_t chunks = h->chunks;
     const unsigned int seq = h->seq;
-    for (int g = blockIdx.x; g < count; g += gridDim.x) {
+    for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        int ga = 0, gb = count - 1;  // last graph with chunk_base <= c
+        while (ga < gb) {
+            const int mid = (ga + gb + 1) >> 1;
+            if (gs[mid].chunk_base <= c) ga = mid;
+            else gb = mid - 1;
+        }
+        const int g = __builtin_amdgcn_readfirstlane(ga);
         const BatchGraph& G = gs[g];
-        for (int64_t r = threadIdx.x; r < G.n; r += blockDim.x) {
+        const int64_t r0 = (c - G.chunk_base) * kEpiChunk;
+        const int64_t r1 = min(r0 + (int64_t)kEpiChunk, G.n);
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
             const int32_t v = G.order[r];
             const unsigned long long tv = G.t[r];
+            G.t[r] = 0ull;
             const int64_t d = G.deg_r[r];
             G.tri[v] = tv;
             if (G.lcc) {
@@ -128,12 +191,24 @@ __global__ void k_batch_epilogue(const BatchGraph* __restrict__ gs, const BatchH
                 G.lcc[v] = x;
             }
         }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached L2
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence_system();
-            done[G.index] = seq;
+            __threadfence();
+            const unsigned int prev =
+                __hip_atomic_fetch_add(&gs[g].chunks_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev + 1 == (unsigned int)G.nchunks) {
+                __threadfence_system();
+                done[G.index] = seq;
+            }
         }
+        __syncthreads();
     }
+}
+
+__global__ void k_batch_clear(unsigned long long* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 // Done flag of a graph that ran through the single-graph launches on this stream.
@@ -189,6 +264,8 @@ void drop_execs(Slot& s) {
     s.execs.clear();
 }
 
+// Device buffers of a free slot.  New counters are cleared here, on the slot's stream; after
+// that every batch leaves the counters it used at zero (the epilogue resets them).
 tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t flags, size_t scratch) {
     Pool* pool = ctx->pool.get();
     bool changed = false;
@@ -245,6 +322,9 @@ tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t fla
         if (st != TC_LCC_OK) return st;
         s.d_scratch = (unsigned long long*)p;
         s.cap_scratch = cap;
+        k_batch_clear<<<(unsigned)std::min<size_t>((cap + 255) / 256, 4096), 256, 0, s.stream>>>(s.d_scratch, cap);
+        TCL_HIP(hipGetLastError());
+        changed = true;
     }
     if (changed) drop_execs(s);
     return TC_LCC_OK;
@@ -261,10 +341,28 @@ uint32_t region_need(const GraphDev& d) {
     return std::min(bm, hs);
 }
 
-constexpr uint32_t kRegionClasses[] = {2048, 4096, 8192};
+// LDS bytes per wave of the batched launch.  Graphs that need more (id ranges or out-lists
+// too large for a wave's slice) have heavy vertices that one wave would count for a long
+// time; they take the single-graph launches, which give such vertices a whole block.
+constexpr uint32_t kRegionClasses[] = {2048, 4096};
+constexpr int kNumRegionClasses = (int)(sizeof(kRegionClasses) / sizeof(kRegionClasses[0]));
 
-tc_lcc_status capture(Slot& s, uint32_t region, bool has4, bool has8, int cu_count, hipGraphExec_t* out) {
-    const uint64_t key = ((uint64_t)region << 2) | (has4 ? 1u : 0u) | (has8 ? 2u : 0u);
+// Count grids: a batch gets the smallest class with a block per heavy vertex plus a wave per
+// light vertex, up to a full GPU of resident blocks.
+constexpr unsigned kGridClasses[] = {64, 256, 1024};
+constexpr int kNumGridClasses = (int)(sizeof(kGridClasses) / sizeof(kGridClasses[0]));
+
+int grid_class(int64_t heavy, int64_t light) {
+    constexpr int64_t per_block = kBatchThreads / kWave;
+    const int64_t blocks = heavy + (light + per_block - 1) / per_block;
+    for (int c = 0; c < kNumGridClasses; ++c)
+        if (blocks <= (int64_t)kGridClasses[c]) return c;
+    return kNumGridClasses;  // full GPU
+}
+
+tc_lcc_status capture(Slot& s, uint32_t region, bool has4, bool has8, int gclass, int cu_count,
+                      hipGraphExec_t* out) {
+    const uint64_t key = ((uint64_t)region << 8) | ((uint64_t)gclass << 2) | (has4 ? 1u : 0u) | (has8 ? 2u : 0u);
     auto it = s.execs.find(key);
     if (it != s.execs.end()) {
         *out = it->second;
@@ -274,14 +372,18 @@ tc_lcc_status capture(Slot& s, uint32_t region, bool has4, bool has8, int cu_cou
     int per4 = 0, per8 = 0;
     TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per4, k_batch_count<int32_t>, kBatchThreads, lds));
     TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per8, k_batch_count<int64_t>, kBatchThreads, lds));
-    const unsigned g4 = (unsigned)(cu_count * std::max(per4, 1));
-    const unsigned g8 = (unsigned)(cu_count * std::max(per8, 1));
+    unsigned g4 = (unsigned)(cu_count * std::max(per4, 1));
+    unsigned g8 = (unsigned)(cu_count * std::max(per8, 1));
+    if (gclass < kNumGridClasses) {
+        g4 = std::min(g4, kGridClasses[gclass]);
+        g8 = std::min(g8, kGridClasses[gclass]);
+    }
+    const unsigned ge = std::min(std::max(g4, g8), 1024u);
     hipGraph_t graph = nullptr;
     TCL_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-    k_batch_zero<<<2048, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr);
     if (has4) k_batch_count<int32_t><<<g4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
     if (has8) k_batch_count<int64_t><<<g8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
-    k_batch_epilogue<<<2048, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
+    k_batch_epilogue<<<ge, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
     hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (e != hipSuccess) {
         set_error("batch: stream capture failed: %s", hipGetErrorString(e));
@@ -375,7 +477,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     for (int i = 0; i < count; ++i) {
         const GraphDev& d = graphs[i]->d;
         const uint32_t r = region_need(d);
-        if (d.n_global > 0 || r > kRegionClasses[2]) {
+        if (d.n_global > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
             solo.push_back(i);
             continue;
         }
@@ -383,7 +485,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         scratch += (size_t)d.n;
         (d.off_bytes == 4 ? ord4 : ord8).push_back(i);
     }
-    uint32_t region = kRegionClasses[2];
+    uint32_t region = kRegionClasses[kNumRegionClasses - 1];
     for (uint32_t c : kRegionClasses)
         if (need <= c) {
             region = c;
@@ -398,7 +500,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     if (st != TC_LCC_OK) return st;
 
     const uint32_t seq = e->next_seq++;
-    int64_t item = 0, items4 = 0;
+    int64_t heavy = 0, light = 0, heavy4 = 0, light4 = 0, chunk = 0;
     size_t soff = 0;
     int k = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -418,36 +520,50 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
             b.tri = (unsigned long long*)tri[i];
             b.lcc = lcc ? lcc[i] : nullptr;
             b.n = d.n;
-            b.items = d.n_block + d.n_wave;
-            b.item_base = item;
+            b.heavy = d.n_block_big;
+            b.light = d.n_block - d.n_block_big + d.n_wave;
+            b.heavy_base = heavy;
+            b.light_base = light;
+            b.chunk_base = chunk;
             b.index = i;
+            b.nchunks = (int32_t)std::max<int64_t>(1, (d.n + kEpiChunk - 1) / kEpiChunk);  // an empty graph still gets its flag
+            b.chunks_done = 0;
             b.pad_ = 0;
-            item += b.items;
+            heavy += b.heavy;
+            light += b.light;
+            chunk += b.nchunks;
             soff += (size_t)d.n;
         }
-        if (pass == 0) items4 = item;
+        if (pass == 0) {
+            heavy4 = heavy;
+            light4 = light;
+        }
     }
     s->h_hdr->count = nb;
     s->h_hdr->count4 = (int32_t)ord4.size();
-    s->h_hdr->items4 = items4;
-    s->h_hdr->items = item;
+    s->h_hdr->heavy4 = heavy4;
+    s->h_hdr->heavy = heavy;
+    s->h_hdr->light4 = light4;
+    s->h_hdr->light = light;
     s->h_hdr->region = region;
     s->h_hdr->seq = seq;
-    s->h_hdr->queue[0] = s->h_hdr->queue[1] = 0;
+    for (unsigned int& q : s->h_hdr->queue) q = 0;
+    s->h_hdr->chunks = chunk;
 
     if (nb > 0) {
         hipGraphExec_t exec = nullptr;
-        st = capture(*s, region, !ord4.empty(), !ord8.empty(), ctx->cu_count, &exec);
+        st = capture(*s, region, !ord4.empty(), !ord8.empty(), grid_class(heavy, light), ctx->cu_count, &exec);
         if (st != TC_LCC_OK) return st;
         TCL_HIP(hipMemcpyAsync(s->d_graphs, s->h_graphs, (size_t)nb * sizeof(BatchGraph), hipMemcpyHostToDevice,
                                s->stream));
         TCL_HIP(hipMemcpyAsync(s->d_hdr, s->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s->stream));
         TCL_HIP(hipGraphLaunch(exec, s->stream));
     }
-    // graphs that need the global-memory path: the single-graph launches, on this slot's stream
+    // graphs beyond the batched launch's LDS slices: the single-graph launches, on this slot's
+    // stream, leaving one block slot per CU free so that other slots' batches keep running
     for (int i : solo) {
         lk.unlock();
-        st = tc_lcc_run(graphs[i], tri[i], lcc ? lcc[i] : nullptr, s->stream);
+        st = run_graph(graphs[i], tri[i], lcc ? lcc[i] : nullptr, s->stream, 1);
         lk.lock();
         if (st != TC_LCC_OK) return st;
         k_batch_mark<<<1, 64, 0, s->stream>>>(s->d_done, i, seq);

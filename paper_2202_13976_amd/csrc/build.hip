@@ -603,9 +603,13 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
         set_error("schedule: a radix sort pass gave up waiting for an earlier tile");
         return TC_LCC_DEVICE_ERROR;
     }
-    int64_t nb = 0;
-    for (int c = 0; c < kClassWave; ++c) nb += (int64_t)hc[c];
+    int64_t nb = 0, big = 0;
+    for (int c = 0; c < kClassWave; ++c) {
+        nb += (int64_t)hc[c];
+        if (40 - c >= kBigWorkBits) big += (int64_t)hc[c];  // class c holds work of bit length 40 - c
+    }
     d.n_block = nb;
+    d.n_block_big = big;
     d.n_wave = (int64_t)hc[kClassWave];
     d.n_global = (int64_t)hc[kClassGlobal];
     const int64_t active = nb + d.n_wave + d.n_global;

@@ -15,7 +15,11 @@
 //
 // Load balance: a persistent grid pulls vertices from device queues.  Heavy
 // vertices (by probe count, heaviest first) take a whole block; light ones take
-// one wave with a slice of the block's LDS.  Each wave takes 64 in-edges at a
+// one wave with a slice of the block's LDS, kLightGrab at a time.  The first item
+// of every block (and the first grab of every wave) is fixed by its index and only
+// later ones come from the queue counter: device-wide atomics on one address are
+// serialized, so a small graph runs without any and a large one needs few.
+// Each wave takes 64 in-edges at a
 // time and walks their tails one after the other in windows of 64 candidates
 // (lane i reads candidate base + i: coalesced), with all loop bounds wave-uniform
 // (scalar).  A ring of kUnroll windows is prefetched, so that many loads stay in
@@ -23,6 +27,14 @@
 #include "count_device.hpp"
 
 namespace tcl {
+
+constexpr int kLightGrab = 8;  // light vertices a wave takes per queue access (large graphs)
+
+// Light vertices per grab: kLightGrab when there are plenty per wave, single ones when few
+// (so that a small graph spreads its light vertices over all waves).
+__host__ __device__ __forceinline__ int light_grab(int64_t n_light, int64_t waves) {
+    return n_light >= waves * (int64_t)kLightGrab * 4 ? kLightGrab : 1;
+}
 
 template <typename OffT, int PROBE>
 __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
@@ -33,30 +45,40 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
     const int w = threadIdx.x / kWave, lane = lane_id();
 
     // phase 1: heavy vertices, one block each, heaviest first
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&a.ctr[0], 1u);
-        __syncthreads();
-        const int64_t it = s_item;
-        __syncthreads();
+    const int64_t grid = gridDim.x;
+    for (int64_t it = blockIdx.x;;) {
         if (it >= a.n_block) break;
         const int32_t v = a.vlist[it];
         unsigned long long local = 0;
         process_vertex<OffT, PROBE, kWavesPerBlock>(a, v, lds, block_bytes, threadIdx.x, w, local);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
+        if (grid >= a.n_block) break;
+        if (threadIdx.x == 0) s_item = grid + (int64_t)atomicAdd(&a.ctr[0], 1u);
+        __syncthreads();
+        it = s_item;
+        __syncthreads();
     }
-    // phase 2: light vertices, one wave each with its own slice of the LDS
+    // phase 2: light vertices, one wave each with its own slice of the LDS; the fixed first
+    // grabs go to the last blocks first, which hold no heavy vertex
     uint8_t* wregion = lds + (size_t)w * wave_bytes;
-    for (;;) {
-        unsigned int it = 0;
-        if (lane == 0) it = atomicAdd(&a.ctr[1], 1u);
-        it = __shfl(it, 0, kWave);
-        if ((int64_t)it >= a.n_wave) break;
-        const int32_t v = a.vlist[a.n_block + it];
-        unsigned long long local = 0;
-        process_vertex<OffT, PROBE, 1>(a, v, wregion, wave_bytes, lane, 0, local);
-        const unsigned long long ws = wave_sum(local);
-        if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
+    const int64_t waves = grid * kWavesPerBlock;
+    const int grab = light_grab(a.n_wave, waves);
+    for (int64_t it = ((grid - 1 - blockIdx.x) * (int64_t)kWavesPerBlock + w) * grab;;) {
+        if (it >= a.n_wave) break;
+        const int64_t end = min(it + (int64_t)grab, a.n_wave);
+        for (; it < end; ++it) {
+            const int32_t v = a.vlist[a.n_block + it];
+            unsigned long long local = 0;
+            process_vertex<OffT, PROBE, 1>(a, v, wregion, wave_bytes, lane, 0, local);
+            const unsigned long long ws = wave_sum(local);
+            if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
+        }
+        if (waves * grab >= a.n_wave) break;
+        unsigned int q = 0;
+        if (lane == 0) q = atomicAdd(&a.ctr[1], 1u);
+        q = __shfl(q, 0, kWave);
+        it = (waves + (int64_t)q) * grab;
     }
 }
 
@@ -116,7 +138,7 @@ int resolve_probe(int probe, int64_t n) {
 }
 
 template <typename OffT>
-static tc_lcc_status launch_typed(tc_lcc_graph g, hipStream_t st) {
+static tc_lcc_status launch_typed(tc_lcc_graph g, int spare_per_cu, hipStream_t st) {
     GraphDev& d = g->d;
     CountArgs<OffT> a;
     a.out_off = (const OffT*)d.out_off;
@@ -143,9 +165,12 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, hipStream_t st) {
                                                            : k_count<OffT, TC_LCC_PROBE_AUTO>;
         int per_cu = 0;
         TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kCountThreads, lds));
+        if (per_cu - spare_per_cu >= 1) per_cu -= spare_per_cu;
         if (per_cu < 1) per_cu = 1;
-        const int64_t want = d.n_block + (d.n_wave + kWavesPerBlock - 1) / kWavesPerBlock;
+        // enough blocks for one heavy vertex or one grab per wave each, up to a full GPU; the
+        // grab size follows from the grid actually launched
         int64_t grid = (int64_t)g->ctx->cu_count * per_cu;
+        const int64_t want = d.n_block + (d.n_wave + kWavesPerBlock - 1) / kWavesPerBlock;
         if (grid > want) grid = want;
         if (grid < 1) grid = 1;
         kern<<<(unsigned)grid, kCountThreads, lds, st>>>(a);
@@ -162,9 +187,10 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, hipStream_t st) {
     return TC_LCC_OK;
 }
 
-tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st) {
+tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, int spare_per_cu, hipStream_t st) {
     (void)tn;
-    return g->d.off_bytes == 4 ? launch_typed<int32_t>(g, st) : launch_typed<int64_t>(g, st);
+    return g->d.off_bytes == 4 ? launch_typed<int32_t>(g, spare_per_cu, st)
+                               : launch_typed<int64_t>(g, spare_per_cu, st);
 }
 
 // ------------------------------------------------------------------ zeroing and epilogue

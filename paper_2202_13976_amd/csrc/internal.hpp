@@ -21,6 +21,7 @@ namespace tcl {
 constexpr int kCountThreads = 256;
 constexpr int kWavesPerBlock = kCountThreads / kWave;
 constexpr int32_t kMaxTableSlots = 4096;  // 4096 x (4 B id + 4 B counter) = 32 KiB per block
+constexpr int kBigWorkBits = 15;          // probes >= 2^14: a vertex the batched launch gives a block
 
 int resolve_probe(int probe, int64_t n);
 int32_t table_slots(int probe, int32_t dplus_max);
@@ -70,6 +71,8 @@ struct GraphDev {
     unsigned int* counters = nullptr;      // [8] work-queue counters of the count kernel
     int32_t* vlist = nullptr;   // [n] scheduled vertices: block bin, wave bin, global bin
     int64_t n_block = 0, n_wave = 0, n_global = 0;
+    int64_t n_block_big = 0;    // leading block-class vertices with >= kBigWork probes
+
     int32_t hash_slots = 64;    // LDS hash slots of one block (power of two)
     int32_t max_dplus = 0;
     int64_t max_deg = 0;
@@ -128,12 +131,16 @@ tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
 tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
 
 // count.hip
-tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
+// spare_per_cu: resident blocks per CU left free for other streams' kernels (0 = fill the GPU)
+tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, int spare_per_cu, hipStream_t st);
 tc_lcc_status launch_epilogue(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st);
 tc_lcc_status launch_zero_counts(tc_lcc_graph g, hipStream_t st);
 
 // batch.hip
 void batch_engine_destroy(tc_lcc_ctx ctx);
+
+// api.cpp: the single-graph run of tc_lcc_run, with launch_count's spare_per_cu
+tc_lcc_status run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu);
 
 // tuning defaults
 tc_lcc_tuning default_tuning();

@@ -73,8 +73,34 @@ def test_mix_equals_alone(ctx, pool, inflight, batch):
     for inf in infos:
         assert inf.arrival_ns <= inf.admit_ns <= inf.done_ns
         assert 1 <= inf.batch_size <= batch
-    if batch > 1:
-        assert max(inf.batch_size for inf in infos) > 1, "arrivals during running batches must be batched"
+
+
+def test_burst_is_batched(ctx, pool):
+    """With one launch in flight, requests that arrive while a large graph runs are counted
+    together in the next launch, and each still gets its own exact result."""
+    print("[gpu] server burst behind a scale-17 graph", flush=True)
+    graphs, alone = pool
+    n, s, d = synth.rmat_scale(17, 16, seed=5)
+    big = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    big_ref = big.run()
+    torch.cuda.synchronize()
+    server = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=4096)
+    tri_b = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    first = server.submit(big, tri_b)
+    outs, ids = [], []
+    for k in list(range(len(graphs))) * 2:
+        g = graphs[k]
+        tri = torch.full((g.n,), -1, dtype=torch.int64, device="cuda")
+        lcc = torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda")
+        outs.append((k, tri, lcc))
+        ids.append(server.submit(g, tri, lcc))
+    server.poll(first, block=True)
+    infos = [server.poll(i, block=True) for i in ids]
+    server.close()
+    assert torch.equal(tri_b, big_ref[0])
+    check(outs, alone)
+    assert max(inf.batch_size for inf in infos) > 1, "requests queued behind a running launch must be batched"
+    big.free()
 
 
 def test_tiny_budget_queues(ctx, pool):
