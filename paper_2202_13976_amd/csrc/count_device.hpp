@@ -153,22 +153,27 @@ __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) 
     return hit;
 }
 
-// Each wave walks the tails of its chunks of 64 in-edges of v and probes every candidate.
+// The waves of a group walk the tails of v's in-edges, 64 in-edges (a chunk) at a time,
+// and probe every candidate in windows of 64 consecutive candidates of one tail.  Wave
+// wig of NWAVES takes tails wig, wig + NWAVES, ... of every chunk, so the waves of a
+// block share each vertex evenly whatever its in-degree, and every tail stays with one
+// wave.
 //
-// Windows of 64 consecutive candidates of one tail come from a generator whose state is
-// wave-uniform (tail j is owned by lane j; the tail's start pointer is formed once per
-// tail), so a window costs a few scalar operations.  A ring of 2 * kUnroll windows is
-// kept in flight: the loads of one half arrive while the other half is probed.  For the
-// rank bitmap the LDS reads of all windows of a half are issued before any is used, so
-// one LDS round trip serves kUnroll windows.  Every hit found here is a triangle with v
-// as its middle vertex, so the chunk's hits are also v's share (`local`).
+// The window generator's state is wave-uniform (tail j is owned by lane j; the tail's
+// start pointer is formed once per tail), so a window costs a few scalar operations.  A
+// ring of 2 * kUnroll windows is kept in flight: the loads of one half arrive while the
+// other half is probed.  For the rank bitmap the LDS reads of all windows of a half are
+// issued before any is used, so one LDS round trip serves kUnroll windows.  Every hit
+// found here is a triangle with v as its middle vertex, so the hits are also v's share
+// (`local`).
 template <typename OffT, int MODE, int NWAVES>
 __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig,
                            unsigned long long& local) {
     constexpr int kRing = 2 * kUnroll;
     const int lane = lane_id();
+    wig = __builtin_amdgcn_readfirstlane(wig);  // wave-uniform: keeps the generator scalar
     const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
-    for (OffT cb = i0 + (OffT)wig * kWave; cb < i1; cb += (OffT)NWAVES * kWave) {
+    for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
         const OffT k = cb + lane;
         const bool ok = k < i1;
         int32_t u = 0;
@@ -201,20 +206,27 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                 gjv = -1;
             }
         };
+        // next window: the next 64 candidates of this tail, else the start of this wave's
+        // next tail
+        auto advance = [&]() {
+            gbase += kWave;
+            if (gbase >= glen) {
+                gbase = 0;
+                gj += NWAVES;
+                fetch_tail();
+            }
+        };
+        gj = wig;
         fetch_tail();
-        // next window: its tail j, the number of lanes holding candidates, and this lane's
-        // candidate (lanes past the tail re-read its last one; they are masked by `lim`)
+        // next window of this wave: its tail j, the number of lanes holding candidates, and
+        // this lane's candidate (lanes past the tail re-read its last one; they are masked by
+        // `lim`); a spent generator yields tail -1
         auto gen = [&](int& j, int& lim) -> int32_t {
             j = gjv;
             lim = glen - gbase;
             const uint32_t off = min((uint32_t)(gbase + lane), (uint32_t)(glen - 1));
             const int32_t x = *(const int32_t*)((const char*)tptr + (off << 2));
-            gbase += kWave;
-            if (gbase >= glen) {
-                gbase = 0;
-                ++gj;
-                fetch_tail();
-            }
+            advance();
             return x;
         };
 
@@ -229,7 +241,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
         auto account = [&](int j, unsigned long long H) {
             if (j != cur_j) {
                 // lane cur_j of `mine` := cur_c (a register write, no memory access)
-                asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(cur_c), "{m0}"(cur_j));
+                asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(__builtin_amdgcn_readfirstlane(cur_c)), "{m0}"(cur_j));
                 cur_j = j;
                 cur_c = 0;
             }
@@ -275,7 +287,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                 }
             }
         }
-        asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(cur_c), "{m0}"(cur_j));
+        asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(__builtin_amdgcn_readfirstlane(cur_c)), "{m0}"(cur_j));
         local += mine;
         if (ok && mine) atomicAdd(&a.t[u], (unsigned long long)mine);
     }
