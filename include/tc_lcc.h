@@ -102,6 +102,7 @@ typedef struct {
     int32_t count_blocks_per_cu; /* resident blocks per compute unit the occupancy query allowed */
     int32_t table_slots;      /* LDS table slots of one block */
     uint64_t push_words;      /* sum over oriented edges (u -> v) of |N+(v)| (whole-list streaming) */
+    int64_t global_vertices;  /* active vertices whose N+(v) exceeds the LDS table (searched in HBM) */
 } tc_lcc_graph_stats;
 
 tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);

@@ -40,7 +40,7 @@ class GraphStats(ctypes.Structure):
                 ("staged_entries", ctypes.c_int64), ("block_vertices", ctypes.c_int64),
                 ("count_grid", ctypes.c_int32), ("count_lds_bytes", ctypes.c_int32),
                 ("count_blocks_per_cu", ctypes.c_int32), ("table_slots", ctypes.c_int32),
-                ("push_words", ctypes.c_uint64)]
+                ("push_words", ctypes.c_uint64), ("global_vertices", ctypes.c_int64)]
 
 
 class Timings(ctypes.Structure):

@@ -304,6 +304,7 @@ extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* o
     out->count_blocks_per_cu = g->d.count_per_cu;
     out->table_slots = g->d.hash_slots;
     out->push_words = g->d.push_words;
+    out->global_vertices = g->d.n_global;
     return TC_LCC_OK;
 }
 

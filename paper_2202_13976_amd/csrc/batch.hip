@@ -335,9 +335,7 @@ tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t fla
 uint32_t region_need(const GraphDev& d) {
     const uint32_t words = (uint32_t)((d.n + 31) / 32);
     const uint32_t bm = bitmap_bytes(words, d.max_dplus);
-    int32_t T = 64;
-    while (T < 2 * d.max_dplus) T <<= 1;
-    const uint32_t hs = 8u * (uint32_t)T;
+    const uint32_t hs = 8u * (uint32_t)hash_table_slots(d.max_dplus);
     return std::min(bm, hs);
 }
 

@@ -560,9 +560,9 @@ __global__ void k_vlist(const uint64_t* __restrict__ keys, int64_t cnt, int bits
         vlist[i] = (int32_t)(keys[i] & mask);
 }
 
-// LDS slots of one block's table: hash tables get twice the list length (load <= 1/2).
+// LDS slots of one block's table: the sorted list itself, or a hash table for the longest list.
 int32_t table_slots(int probe, int32_t dplus_max) {
-    int32_t need = probe == TC_LCC_PROBE_SORTED ? dplus_max : 2 * dplus_max;
+    int32_t need = probe == TC_LCC_PROBE_SORTED ? dplus_max : hash_table_slots(dplus_max);
     // every wave's slice of the table holds at least the 64 slots of the smallest hash table
     int32_t s = 64 * kWavesPerBlock;
     while (s < need && s < kMaxTableSlots) s <<= 1;
@@ -573,9 +573,9 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     GraphDev& d = g->d;
     const int probe = resolve_probe(tn.probe, d.n);
     d.hash_slots = table_slots(probe, d.max_dplus);
-    const int32_t per_entry = probe == TC_LCC_PROBE_SORTED ? 1 : 2;
-    const int32_t block_cap = d.hash_slots / per_entry;
-    const int32_t wave_cap = (d.hash_slots / kWavesPerBlock) / per_entry;
+    const bool sorted = probe == TC_LCC_PROBE_SORTED;
+    const int32_t block_cap = sorted ? d.hash_slots : hash_capacity(d.hash_slots);
+    const int32_t wave_cap = sorted ? d.hash_slots / kWavesPerBlock : hash_capacity(d.hash_slots / kWavesPerBlock);
     Temps tmp{g->ctx->pool.get(), {}};
     const size_t n = (size_t)d.n;
     uint64_t *ka, *kb, *res;

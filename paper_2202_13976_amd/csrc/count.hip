@@ -84,7 +84,8 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
 
 // Vertices whose N+(v) exceeds the LDS table: binary search straight in N+(v) in
 // global memory, one wave per in-edge chunk of 64, per-entry counts go to t(w)
-// directly.  Only taken when |N+(v)| > 2048 (hash) or 4096 (sorted).
+// directly.  Only taken when |N+(v)| exceeds the largest table: 2048 keys (hash of 4096
+// slots at load 1/2) or 4096 (sorted list).
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
     const int w = threadIdx.x / kWave, lane = lane_id();

@@ -336,8 +336,7 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
             if (j == 0 || ((uint32_t)(nv[j - 1] - tb.base) >> 5) != (i >> 5)) tb.first[i >> 5] = (uint16_t)j;
         }
     } else if (mode == TC_LCC_PROBE_HASH) {
-        int32_t T = 64;
-        while (T < 2 * dv) T <<= 1;
+        const int32_t T = hash_table_slots(dv);
         const uint32_t nb = (uint32_t)T >> 2;
         tb.T = T;
         tb.nb_mask = nb - 1;

@@ -26,6 +26,17 @@ constexpr int kBigWorkBits = 15;          // probes >= 2^14: a vertex the batche
 int resolve_probe(int probe, int64_t n);
 int32_t table_slots(int probe, int32_t dplus_max);
 
+// Bucket hash of a list of dv keys: a power of two >= 2 dv slots (load <= 1/2), at least 64.
+// capacity(T) is the longest list a table of T slots takes.  (A load of 2/3 halves the
+// tables of the largest lists but was slower at R-MAT scale 23: more vertices leave the
+// bitmap and the wave slices.)
+__host__ __device__ inline int32_t hash_table_slots(int32_t dv) {
+    int32_t T = 64;
+    while (T < 2 * dv) T <<= 1;
+    return T;
+}
+__host__ __device__ inline int32_t hash_capacity(int32_t T) { return T / 2; }
+
 // ------------------------------------------------------------------ device memory pool
 // Caching allocator per context.  Blocks are rounded to size classes and kept on
 // free lists after release; the budget covers blocks in use plus cached blocks.

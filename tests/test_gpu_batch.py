@@ -59,15 +59,15 @@ def test_batch_matches_oracle(ctx):
 
 
 def test_batch_mixed_widths_and_global_path(ctx):
-    """4- and 8-byte offsets in one batch, plus a clique whose out-lists exceed the LDS table."""
-    print("[gpu] batch mixed widths + K2200", flush=True)
+    """4- and 8-byte offsets in one batch, plus K_2800, whose out-lists exceed the largest LDS
+    table (checked against the closed form for K_n, which pins the oracle too)."""
+    print("[gpu] batch mixed widths + K2800", flush=True)
     raw = [synth.rmat_scale(11, 16, seed=s) for s in (1, 2, 3)] + [(5000, *synth.er(5000, 40000, seed=4))]
     widths = [4, 8, 4, 8]
-    pairs = list(itertools.combinations(range(2200), 2))
-    a = np.array(pairs, dtype=np.int32)
-    raw.append((2200, a[:, 0].copy(), a[:, 1].copy()))
-    widths.append(8)
+    a = np.array(list(itertools.combinations(range(2800), 2)), dtype=np.int32)
     graphs = [build(ctx, n, s, d, ob) for (n, s, d), ob in zip(raw, widths)]
+    graphs.append(build(ctx, 2800, a[:, 0], a[:, 1], 8))
+    assert graphs[-1].info().global_vertices > 0
     tris, lccs = outputs(graphs)
     tk = ctx.batch_submit(graphs, tris, lccs)
     assert ctx.batch_poll(tk, block=True)[0]
@@ -75,6 +75,7 @@ def test_batch_mixed_widths_and_global_path(ctx):
         t_ref, l_ref = oracle.tc_lcc(n, s, d)
         np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
         assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
+    assert bool((tris[-1] == 2799 * 2798 // 2).all()) and bool((lccs[-1] == 1.0).all())
     for g in graphs:
         g.free()
 
@@ -127,9 +128,9 @@ def test_batch_progress_per_graph(ctx):
     print("[gpu] batch progress flags", flush=True)
     raw = [synth.rmat_scale(10, 16, seed=s) for s in (1, 2, 3)]
     pairs = np.array(list(itertools.combinations(range(2200), 2)), dtype=np.int32)
-    raw.insert(1, (2200, pairs[:, 0].copy(), pairs[:, 1].copy()))        # beyond the LDS table
+    raw.insert(1, (2200, pairs[:, 0].copy(), pairs[:, 1].copy()))        # beyond a batched wave's slice
     sub = pairs[pairs[:, 1] < 2100]
-    raw.insert(0, (2100, sub[:, 0].copy(), sub[:, 1].copy()))            # beyond it, less work
+    raw.insert(0, (2100, sub[:, 0].copy(), sub[:, 1].copy()))            # likewise, less work
     graphs = [build(ctx, n, s, d, 4) for n, s, d in raw]
     single = [g.run() for g in graphs]
     torch.cuda.synchronize()

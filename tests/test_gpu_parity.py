@@ -137,11 +137,36 @@ def test_edge_cases(ctx):
         check(ctx, n, s, d, label)
 
 
+def clique(n):
+    a = np.array(list(itertools.combinations(range(n), 2)), dtype=np.int32)
+    return a[:, 0].copy(), a[:, 1].copy()
+
+
 def test_large_clique_global_path(ctx):
-    """K_2200: |N+(v)| reaches 2199, beyond the LDS table, so the global-memory path runs."""
-    n = 2200
-    s, d = arr(list(itertools.combinations(range(n), 2)))
-    check(ctx, n, s, d, "K2200", offset_bytes=8)
+    """K_2800: |N+(v)| reaches 2799, beyond the largest LDS table (2048 keys), so the
+    global-memory path runs.  Reference: the closed form for K_n (t = C(n-1, 2), LCC = 1),
+    which the oracle's own pins establish; running the oracle on 3.9 M edges would be slow."""
+    n = 2800
+    say(f"[gpu] K{n} (global path)")
+    s, d = clique(n)
+    g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    assert g.info().global_vertices > 0, "the clique must take the global-memory path"
+    tri, lcc = g.run()
+    torch.cuda.synchronize()
+    assert bool((tri == (n - 1) * (n - 2) // 2).all())
+    assert bool((lcc == 1.0).all())
+    g.free()
+    # the same clique with 4-byte offsets and the sorted-list probe (a 4096-key table holds it)
+    probe0 = ctx.tuning().probe
+    ctx.set_tuning(probe=pkg.PROBE_SORTED)
+    try:
+        g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=4)
+        tri, lcc = g.run()
+        torch.cuda.synchronize()
+        assert bool((tri == (n - 1) * (n - 2) // 2).all()) and bool((lcc == 1.0).all())
+        g.free()
+    finally:
+        ctx.set_tuning(probe=probe0)
 
 
 def test_host_inputs_and_repeats(ctx):
