@@ -171,6 +171,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                            unsigned long long& local) {
     constexpr int kRing = 2 * kUnroll;
     const int lane = lane_id();
+    const uint32_t lane4 = (uint32_t)lane * 4u;
     wig = __builtin_amdgcn_readfirstlane(wig);  // wave-uniform: keeps the generator scalar
     const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
     for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
@@ -224,8 +225,8 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
         auto gen = [&](int& j, int& lim) -> int32_t {
             j = gjv;
             lim = glen - gbase;
-            const uint32_t off = min((uint32_t)(gbase + lane), (uint32_t)(glen - 1));
-            const int32_t x = *(const int32_t*)((const char*)tptr + (off << 2));
+            const uint32_t off4 = min((uint32_t)gbase * 4u + lane4, (uint32_t)(glen - 1) * 4u);
+            const int32_t x = *(const int32_t*)((const char*)tptr + off4);
             advance();
             return x;
         };
@@ -264,10 +265,17 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                         const int sl = h * kUnroll + q;
                         asm volatile("" : "+v"(fs[q]));  // keep the read ahead of the hit branch
                         if (js[sl] >= 0) {
-                            const uint32_t bit = ii[q] & 31u;
-                            const bool hit = lane < lims[sl] && ((wd[q] >> bit) & 1u);
-                            const unsigned long long H = __builtin_amdgcn_ballot_w64(hit);
-                            if (hit) atomicAdd(&tb.cnt[fs[q] + (uint32_t)__popc(wd[q] & ((1u << bit) - 1u))], 1u);
+                            // v_bfe takes offset and width modulo 32: bit ii % 32 of the word,
+                            // and the bits below it
+                            const bool in_tail = lane < lims[sl];
+                            const bool set = __builtin_amdgcn_ubfe(wd[q], ii[q], 1u) != 0u;
+                            // two ballots of plain compares, combined in scalar registers
+                            const unsigned long long H =
+                                __builtin_amdgcn_ballot_w64(in_tail) & __builtin_amdgcn_ballot_w64(set);
+                            if (in_tail && set) {
+                                const uint32_t pos = (uint32_t)__popc(__builtin_amdgcn_ubfe(wd[q], 0u, ii[q])) + fs[q];
+                                atomicAdd((uint32_t*)((char*)tb.cnt + (pos << 2)), 1u);
+                            }
                             account(js[sl], H);
                         }
                         xs[sl] = gen(js[sl], lims[sl]);
