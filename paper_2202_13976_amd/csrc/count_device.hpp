@@ -93,14 +93,14 @@ struct Win {
 // LDS view of the staged N+(v) for one probe method.
 //   hash:   keys[T] (-1 = empty) and cnt[T], 4-slot buckets
 //   sorted: keys[dv] = N+(v) and cnt[dv], binary search
-//   bitmap: bm[words] over ranks (v, vmax] plus one zero guard word, first[words] = index
-//           in N+(v) of the first entry in each word, cnt[dv]; the entry index of a hit is
-//           first + popcount.  Candidates outside the range clamp onto the guard word.
+//   bitmap: bm[2 (words + 1)]: per 32-rank word of the range (v, vmax] the bits and the
+//           index in N+(v) of the word's first entry, plus one zero guard word; cnt[dv].
+//           The entry index of a hit is first + popcount of the bits below it; candidates
+//           outside the range clamp onto the guard word.  One 8-byte LDS read per probe.
 struct Table {
     int32_t* keys;
     uint32_t* cnt;
     uint32_t* bm;
-    uint16_t* first;
     int32_t T;
     uint32_t nb_mask;
     int logNB;
@@ -257,8 +257,9 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                     for (int q = 0; q < kUnroll; ++q) {
                         ii[q] = (uint32_t)(xs[h * kUnroll + q] - tb.base);  // candidates are ranks above v
                         const uint32_t wi = min(ii[q] >> 5, tb.words);      // beyond the range: guard word
-                        wd[q] = tb.bm[wi];
-                        fs[q] = tb.first[wi];
+                        const uint2 e = *reinterpret_cast<const uint2*>(tb.bm + 2 * wi);  // word, first index
+                        wd[q] = e.x;
+                        fs[q] = e.y;
                     }
 #pragma unroll
                     for (int q = 0; q < kUnroll; ++q) {
@@ -303,7 +304,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
 
 // Bytes of the bitmap layout for `words` bitmap words (plus the guard word) and dv counters.
 __host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
-    return ((6u * (words + 1u) + 3u) & ~3u) + 4u * (uint32_t)dv;
+    return 8u * (words + 1u) + 4u * (uint32_t)dv;
 }
 
 // One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
@@ -333,15 +334,14 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
     // ---- stage N+(v)
     if (mode == TC_LCC_PROBE_BITMAP) {
         tb.bm = (uint32_t*)region;
-        tb.first = (uint16_t*)(tb.bm + tb.words + 1);
-        tb.cnt = (uint32_t*)(region + ((6u * (tb.words + 1u) + 3u) & ~3u));
-        for (uint32_t s = gtid; s <= tb.words; s += gsize) tb.bm[s] = 0u;  // with the guard word
+        tb.cnt = (uint32_t*)(region + 8u * (tb.words + 1u));
+        for (uint32_t s = gtid; s <= tb.words; s += gsize) tb.bm[2 * s] = 0u;  // with the guard word
         for (int j = gtid; j < dv; j += gsize) tb.cnt[j] = 0u;
         group_sync<NWAVES>();
         for (int j = gtid; j < dv; j += gsize) {
             const uint32_t i = (uint32_t)(nv[j] - tb.base);
-            atomicOr(&tb.bm[i >> 5], 1u << (i & 31u));
-            if (j == 0 || ((uint32_t)(nv[j - 1] - tb.base) >> 5) != (i >> 5)) tb.first[i >> 5] = (uint16_t)j;
+            atomicOr(&tb.bm[2 * (i >> 5)], 1u << (i & 31u));
+            if (j == 0 || ((uint32_t)(nv[j - 1] - tb.base) >> 5) != (i >> 5)) tb.bm[2 * (i >> 5) + 1] = (uint32_t)j;
         }
     } else if (mode == TC_LCC_PROBE_HASH) {
         const int32_t T = hash_table_slots(dv);
