@@ -146,45 +146,59 @@ __global__ void k_split_adj(const uint64_t* __restrict__ ok, size_t m, int bits,
 // oriented edge i = (u -> v) at position i of N+(u): its tail is adj[i+1 .. out_off[u+1]).
 // Kept (it can close a triangle) if the tail is nonempty and N+(v) is nonempty.
 template <typename OffT>
-struct KeptFlag {
-    const uint64_t* ok;
-    size_t m;
-    int bits;
-    const OffT* out_off;
-    const int32_t* dplus;
-    __device__ uint32_t operator()(size_t i) const {
-        if (i >= m) return 0;
-        const uint64_t x = ok[i];
-        const uint64_t mask = (1ull << bits) - 1;
-        const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
-        return ((int64_t)out_off[u + 1] - (int64_t)i - 1 > 0 && dplus[v] > 0) ? 1u : 0u;
-    }
-};
-
-template <typename OffT>
-__global__ void k_kept_words(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
-                             const int32_t* __restrict__ dplus, const uint32_t* __restrict__ pos,
-                             uint64_t* __restrict__ words) {
+__global__ void k_kept_flags(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
+                             const int32_t* __restrict__ dplus, uint8_t* __restrict__ flag) {
     const uint64_t mask = (1ull << bits) - 1;
     GRID_STRIDE(i, m) {
         const uint64_t x = ok[i];
         const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
-        if ((int64_t)out_off[u + 1] - (int64_t)i - 1 > 0 && dplus[v] > 0)
-            words[pos[i]] = ((uint64_t)v << 32) | (uint64_t)i;
+        flag[i] = ((int64_t)out_off[u + 1] - (int64_t)i - 1 > 0 && dplus[v] > 0) ? 1 : 0;
     }
 }
 
-// in-edge k (sorted by v, then by position i): u from the oriented key, tail [i+1, out_off[u+1])
+struct U8In {
+    const uint8_t* p;
+    size_t n;
+    __device__ uint32_t operator()(size_t i) const { return i < n ? (uint32_t)p[i] : 0u; }
+};
+
+// What the reverse lists need of kept in-edge p: u, the tail's start in adj and its length.
+struct KeptEdge {
+    int32_t u;
+    int32_t len;
+    uint64_t start;
+};
+
+// Kept edge i gets kept index p = pos[i]: its sort word (v, p) and its payload, both written
+// in edge order (so sequentially); the sort by v then permutes only the words.
 template <typename OffT>
-__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const uint64_t* __restrict__ ok,
-                          int bits, const OffT* __restrict__ out_off, int32_t* __restrict__ in_u,
-                          OffT* __restrict__ in_start, int32_t* __restrict__ in_len) {
+__global__ void k_kept_emit(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
+                            const uint8_t* __restrict__ flag, const uint32_t* __restrict__ pos,
+                            uint64_t* __restrict__ words, KeptEdge* __restrict__ pay) {
+    const uint64_t mask = (1ull << bits) - 1;
+    GRID_STRIDE(i, m) {
+        if (!flag[i]) continue;
+        const uint64_t x = ok[i];
+        const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
+        const uint32_t p = pos[i];
+        words[p] = ((uint64_t)v << 32) | (uint64_t)p;
+        KeptEdge e;
+        e.u = (int32_t)u;
+        e.len = (int32_t)((int64_t)out_off[u + 1] - (int64_t)i - 1);
+        e.start = (uint64_t)i + 1;
+        pay[p] = e;
+    }
+}
+
+// in-edge k (sorted by v, then by kept index, so by u): one gather of its payload
+template <typename OffT>
+__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const KeptEdge* __restrict__ pay,
+                          int32_t* __restrict__ in_u, OffT* __restrict__ in_start, int32_t* __restrict__ in_len) {
     GRID_STRIDE(k, kept) {
-        const uint64_t i = words[k] & 0xffffffffull;
-        const int64_t u = (int64_t)(ok[i] >> bits);
-        in_u[k] = (int32_t)u;
-        in_start[k] = (OffT)(i + 1);
-        in_len[k] = (int32_t)((int64_t)out_off[u + 1] - (int64_t)i - 1);
+        const KeptEdge e = pay[words[k] & 0xffffffffull];
+        in_u[k] = e.u;
+        in_start[k] = (OffT)e.start;
+        in_len[k] = e.len;
     }
 }
 
@@ -443,12 +457,18 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     for (uint64_t* b : {ka, kb, kc})
         if (b != osorted) (wa ? wb : wa) = b;
     uint32_t kept = 0;
+    KeptEdge* pay = nullptr;
     if (m > 0) {
-        TCL_HIP(exclusive_scan<uint32_t>(KeptFlag<OffT>{osorted, m, bits, out_off, d.dplus}, m + 1, pos, scan32, st));
-        k_kept_words<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, pos, wa);
+        uint8_t* flag;
+        TCL_TRY(tmp.get(m, &flag));
+        k_kept_flags<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, flag);
         TCL_HIP(hipGetLastError());
+        TCL_HIP(exclusive_scan<uint32_t>(U8In{flag, m}, m + 1, pos, scan32, st));
         TCL_HIP(hipMemcpyAsync(&kept, pos + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipStreamSynchronize(st));
+        TCL_TRY(tmp.get(std::max<size_t>(kept, 1), &pay));
+        k_kept_emit<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, flag, pos, wa, pay);
+        TCL_HIP(hipGetLastError());
     }
     d.m_in_kept = (int64_t)kept;
     const size_t KE = std::max<size_t>((size_t)kept, 1);
@@ -469,8 +489,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_HIP(hipGetLastError());
     TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{din, n}, N + 1, in_off, scanO, st));
     if (kept > 0) {
-        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, osorted, bits, out_off, d.in_u,
-                                                                 in_start, d.in_len);
+        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, pay, d.in_u, in_start, d.in_len);
         TCL_HIP(hipGetLastError());
     }
     uint64_t* prefix = (ws == wa) ? wb : wa;  // kept + 1 prefix sums of the tail lengths
