@@ -146,14 +146,33 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
         batched()
         t_batch.append(time.perf_counter() - t0)
     same = all(torch.equal(a, b) for a, b in zip(tris, loop_tris))
+    tl, tb = float(np.median(t_loop)), float(np.median(t_batch))
+    # the autotuner on the batched launch's knobs, then the same measurement again
+    log_fn("[bench] autotuning the batched launch")
+    default = ctx.tuning().as_dict()
+    t0 = time.perf_counter()
+    tuned = ctx.autotune(graphs, what=2, reps=3)
+    tune_s = time.perf_counter() - t0
+    for t in tris:
+        t.fill_(-1)
+    t_tuned = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        batched()
+        t_tuned.append(time.perf_counter() - t0)
+    same_tuned = all(torch.equal(a, b) for a, b in zip(tris, loop_tris))
+    ctx.set_tuning(**default)
     for g in graphs:
         g.free()
-    tl, tb = float(np.median(t_loop)), float(np.median(t_batch))
+    tt = float(np.median(t_tuned))
     return {"workload": "4096 graphs, n log-uniform in [64, 16384], half uniform (avg degree 8-32), "
                         "half R-MAT (EF 8-16), int32 offsets",
             "graphs": len(specs), "m_total": m_total,
             "per_graph_ms": tl * 1e3, "batched_ms": tb * 1e3, "speedup": tl / tb,
-            "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same)}
+            "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same),
+            "autotuned": {"batch_grab": tuned.batch_grab, "batch_heavy_bits": tuned.batch_heavy_bits,
+                          "batched_ms": tt * 1e3, "speedup": tl / tt, "tuning_seconds": tune_s,
+                          "results_identical": bool(same_tuned)}}
 
 
 def run_timing(ctx, torch, n, src, dst, offset_bytes, tri, lcc, warm: int = 3, lo: int = 10, hi: int = 200):

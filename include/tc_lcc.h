@@ -200,26 +200,51 @@ tc_lcc_status tc_lcc_server_destroy(tc_lcc_server s);
 /* ------------------------------------------------------------------ tuning */
 
 typedef enum {
-    TC_LCC_PROBE_AUTO = 0,   /* hash for large id ranges, bitmap when n is small */
-    TC_LCC_PROBE_HASH = 1,   /* open-addressing hash of N+(v) in LDS */
-    TC_LCC_PROBE_SORTED = 2, /* sorted N+(v) in LDS, binary search (Sec. II-C1) */
-    TC_LCC_PROBE_BITMAP = 3, /* bitmap of N+(v) over [0, n) in LDS with rank counts */
-    TC_LCC_PROBE_MERGE = 4   /* no staging: wave merge-path SSI per edge (Sec. II-C2) */
+    TC_LCC_PROBE_AUTO = 0,   /* per vertex: rank bitmap of N+(v) when it fits LDS, else bucket hash */
+    TC_LCC_PROBE_HASH = 1,   /* bucket hash of N+(v) in LDS for every vertex */
+    TC_LCC_PROBE_SORTED = 2, /* sorted N+(v) in LDS, binary search per candidate (Sec. II-C1) */
+    TC_LCC_PROBE_BITMAP = 3, /* same as AUTO (the bitmap is taken wherever it fits) */
+    TC_LCC_PROBE_MERGE = 4   /* not built: set_tuning returns UNSUPPORTED */
 } tc_lcc_probe;
 
 typedef struct {
     int32_t probe;            /* tc_lcc_probe */
-    int32_t group;            /* 0 auto, 1 every vertex to one wave, 2 every vertex to one block */
-    int64_t wave_work_max;    /* vertices with at most this many probes go to one wave */
-    int32_t wave_outdeg_max;  /* ... and at most this |N+(v)| */
-    int32_t block_threads;    /* 256, 512 or 1024 */
-    int32_t merge_ratio_x100; /* MERGE: Eq. 3 cut, 100 * ratio; 0 = log2|B| - 1 */
-    int32_t reserved[7];
+    int32_t group;            /* 0 by work, 1 every vertex to one wave, 2 every vertex to one block */
+    int64_t wave_work_max;    /* group 0: vertices with at most this many probes go to one wave */
+    int32_t wave_outdeg_max;  /* ... and at most this |N+(v)| (0: what a wave's LDS slice holds) */
+    int32_t block_threads;    /* threads per count block: 256 (the only value built; 0 = 256) */
+    int32_t merge_ratio_x100; /* reserved for a merge strategy; must be 0 */
+    int32_t batch_grab;       /* batched launch: light vertices a wave takes per queue access
+                                 when there are plenty (1..64; 0 = 8) */
+    int32_t batch_heavy_bits; /* batched launch: vertices with >= 2^(bits-1) probes get a block
+                                 (1..40; 0 = 15) */
+    int32_t reserved[5];      /* must be 0 */
 } tc_lcc_tuning;
 
-/* Read or replace the context's tuning.  Results never depend on it. */
+/* Read or replace the context's tuning.  Results never depend on it.  INVALID_ARGUMENT for
+ * values out of range, UNSUPPORTED for the merge strategy. */
 tc_lcc_status tc_lcc_get_tuning(tc_lcc_ctx ctx, tc_lcc_tuning* out);
 tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* in);
+
+/* Autotuner.  Times candidate settings on the given graphs (built in ctx) and installs the
+ * fastest in ctx:
+ *   what & 1: single-graph launches: wave_work_max in {1024 .. 16384} and probe in
+ *             {AUTO, HASH} (the bin boundary and the probe strategy), scored by the sum
+ *             over the graphs of the median tc_lcc_run time (HIP events, reps runs);
+ *   what & 2: the batched launch over all the graphs: batch_grab in {1, 4, 8, 16}, then
+ *             batch_heavy_bits in {12, 13, 14, 15, 16, 18}, scored by the median wall
+ *             time of submit + poll (reps runs).
+ * Every candidate's per-vertex counts are compared with those of the setting in force when
+ * the call began; any difference returns DEVICE_ERROR (results must not depend on tuning).
+ * *out (may be NULL) receives the installed setting.  If json_path is not NULL the setting
+ * is written there as JSON with the device's name and the measured times.  The graphs
+ * must not be in use by other work during the call.  Synchronous. */
+tc_lcc_status tc_lcc_autotune(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs, int what, int reps,
+                              const char* json_path, tc_lcc_tuning* out);
+
+/* Install a setting written by tc_lcc_autotune.  UNSUPPORTED if it was tuned on a device of
+ * another name; INVALID_ARGUMENT if the file cannot be read or parsed. */
+tc_lcc_status tc_lcc_tuning_load(tc_lcc_ctx ctx, const char* json_path);
 
 /* ------------------------------------------------------------------ profiling */
 

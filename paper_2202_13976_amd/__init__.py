@@ -11,6 +11,7 @@ Entry points mirror include/tc_lcc.h:
     Graph.run(tri, lcc, stream)        tc_lcc_run
     Context.batch_submit / batch_poll  tc_lcc_batch_submit / poll
     Context.batch_progress             tc_lcc_batch_progress
+    Context.autotune / load_tuning     tc_lcc_autotune / tc_lcc_tuning_load
 """
 from __future__ import annotations
 
@@ -55,7 +56,11 @@ class Timings(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("probe", ctypes.c_int32), ("group", ctypes.c_int32), ("wave_work_max", ctypes.c_int64),
                 ("wave_outdeg_max", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("merge_ratio_x100", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("merge_ratio_x100", ctypes.c_int32), ("batch_grab", ctypes.c_int32),
+                ("batch_heavy_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class RequestInfo(ctypes.Structure):
@@ -67,7 +72,7 @@ _lib = None
 EXPORTS = [
     "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_build_csr", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
-    "tc_lcc_batch_progress",
+    "tc_lcc_batch_progress", "tc_lcc_autotune", "tc_lcc_tuning_load",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
     "tc_lcc_server_create", "tc_lcc_server_submit", "tc_lcc_server_poll", "tc_lcc_server_destroy",
     "tc_lcc_status_string", "tc_lcc_last_error",
@@ -95,6 +100,8 @@ def lib():
     L.tc_lcc_batch_submit.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(u64)]
     L.tc_lcc_batch_poll.argtypes = [vp, u64, i32, ctypes.POINTER(i32)]
     L.tc_lcc_batch_progress.argtypes = [vp, u64, i32, ctypes.POINTER(ctypes.c_uint8)]
+    L.tc_lcc_autotune.argtypes = [vp, i32, vp, i32, i32, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+    L.tc_lcc_tuning_load.argtypes = [vp, ctypes.c_char_p]
     L.tc_lcc_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.tc_lcc_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.tc_lcc_set_profiling.argtypes = [vp, i32]
@@ -258,6 +265,20 @@ class Context:
             return False, int(done.value)
         _check(s, "tc_lcc_batch_poll")
         return True, int(done.value)
+
+    def autotune(self, graphs, what: int = 3, reps: int = 3, path: str | None = None) -> Tuning:
+        """Time candidate settings on `graphs` and install the fastest (tc_lcc_autotune):
+        what & 1 single-graph bins/probe, what & 2 the batched launch's knobs."""
+        count = len(graphs)
+        gh = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
+        t = Tuning()
+        _check(lib().tc_lcc_autotune(self.handle, count, gh, what, reps, path.encode() if path else None,
+                                     ctypes.byref(t)), "tc_lcc_autotune")
+        return t
+
+    def load_tuning(self, path: str):
+        """Install a setting saved by autotune (tc_lcc_tuning_load)."""
+        _check(lib().tc_lcc_tuning_load(self.handle, path.encode()), "tc_lcc_tuning_load")
 
     def batch_progress(self, ticket: int, count: int):
         """Per-graph completion flags (list of bool, submission order) of an unreleased ticket."""

@@ -27,6 +27,8 @@ tc_lcc_tuning default_tuning() {
     t.wave_outdeg_max = 0;
     t.block_threads = 256;
     t.merge_ratio_x100 = 0;
+    t.batch_grab = 8;
+    t.batch_heavy_bits = kBigWorkBits;
     return t;
 }
 
@@ -203,8 +205,16 @@ extern "C" tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* 
         set_error("tc_lcc_set_tuning: null argument");
         return TC_LCC_INVALID_ARGUMENT;
     }
-    if (in->probe < 0 || in->probe > TC_LCC_PROBE_MERGE || in->group < 0 || in->group > 2 ||
-        in->wave_work_max < 0 || (in->block_threads != 0 && in->block_threads != 256)) {
+    if (in->probe == TC_LCC_PROBE_MERGE || in->merge_ratio_x100 != 0) {
+        set_error("tc_lcc_set_tuning: the merge strategy is not built");
+        return TC_LCC_UNSUPPORTED;
+    }
+    bool reserved_zero = true;
+    for (int32_t r : in->reserved) reserved_zero = reserved_zero && r == 0;
+    if (in->probe < 0 || in->probe > TC_LCC_PROBE_BITMAP || in->group < 0 || in->group > 2 ||
+        in->wave_work_max < 0 || in->wave_outdeg_max < 0 || (in->block_threads != 0 && in->block_threads != 256) ||
+        in->batch_grab < 0 || in->batch_grab > 64 || in->batch_heavy_bits < 0 || in->batch_heavy_bits > 40 ||
+        !reserved_zero) {
         set_error("tc_lcc_set_tuning: value out of range");
         return TC_LCC_INVALID_ARGUMENT;
     }

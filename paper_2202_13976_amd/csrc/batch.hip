@@ -25,7 +25,6 @@ namespace tcl {
 
 constexpr int kBatchSlots = 4;
 constexpr int kBatchThreads = 256;
-constexpr int kBatchGrab = 8;  // items a wave takes per queue access
 constexpr int kEpiChunk = 4096;  // vertices per epilogue work item
 
 struct BatchGraph {
@@ -62,6 +61,8 @@ struct BatchHeader {
     uint32_t seq;         // submission number, written to the done flags
     unsigned int queue[4];  // [2 * which]: heavy items, [2 * which + 1]: light grabs taken from the queue
     int64_t chunks;       // epilogue chunks of all graphs
+    int32_t grab;         // light vertices per queue access when there are plenty
+    int32_t pad_;
 };
 
 template <typename OffT>
@@ -97,7 +98,7 @@ __device__ __forceinline__ int batch_graph_of(const BatchGraph* __restrict__ gs,
 // Two phases, as in the single-graph kernel: the heavy vertices of all graphs (those with at
 // least 2^14 probes), one block each (the block's whole LDS is the table), taken one at a
 // time; then all others, one wave each in its slice of the LDS (every vertex of a batched
-// graph fits a slice), taken kBatchGrab at a time when there are plenty.
+// graph fits a slice), taken several at a time (the tuning's batch_grab) when there are plenty.
 template <typename OffT>
 __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph* __restrict__ gs, BatchHeader* h,
                                                                int which) {
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
     const int64_t waves = grid * (kBatchThreads / kWave);
     // light grabs: several items when there are plenty per wave, single ones when few; the
     // fixed first grabs go to the last blocks first, which hold no heavy vertex
-    const int grab = (hi - lo) >= waves * (int64_t)kBatchGrab * 4 ? kBatchGrab : 1;
+    const int grab = (hi - lo) >= waves * (int64_t)h->grab * 4 ? h->grab : 1;
     for (int64_t item = lo + ((grid - 1 - blockIdx.x) * (int64_t)(kBatchThreads / kWave) + w) * grab;;) {
         if (item >= hi) break;
         const int64_t end = min(item + (int64_t)grab, hi);
@@ -497,6 +498,12 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), (size_t)count, std::max<size_t>(scratch, 1));
     if (st != TC_LCC_OK) return st;
 
+    int grab = 8, heavy_bits = kBigWorkBits;
+    {
+        std::lock_guard<std::mutex> tl(ctx->mu);
+        if (ctx->tuning.batch_grab > 0) grab = ctx->tuning.batch_grab;
+        if (ctx->tuning.batch_heavy_bits > 0) heavy_bits = ctx->tuning.batch_heavy_bits;
+    }
     const uint32_t seq = e->next_seq++;
     int64_t heavy = 0, light = 0, heavy4 = 0, light4 = 0, chunk = 0;
     size_t soff = 0;
@@ -518,8 +525,11 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
             b.tri = (unsigned long long*)tri[i];
             b.lcc = lcc ? lcc[i] : nullptr;
             b.n = d.n;
-            b.heavy = d.n_block_big;
-            b.light = d.n_block - d.n_block_big + d.n_wave;
+            // heavy: the leading work classes, those with >= 2^(heavy_bits - 1) probes
+            int64_t big = 0;
+            for (int c = 0; c <= 40 - heavy_bits && c < 48; ++c) big += d.class_count[c];
+            b.heavy = big;
+            b.light = d.n_block - big + d.n_wave;
             b.heavy_base = heavy;
             b.light_base = light;
             b.chunk_base = chunk;
@@ -547,6 +557,8 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     s->h_hdr->seq = seq;
     for (unsigned int& q : s->h_hdr->queue) q = 0;
     s->h_hdr->chunks = chunk;
+    s->h_hdr->grab = grab;
+    s->h_hdr->pad_ = 0;
 
     if (nb > 0) {
         hipGraphExec_t exec = nullptr;

@@ -594,7 +594,8 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     d.hash_slots = table_slots(probe, d.max_dplus);
     const bool sorted = probe == TC_LCC_PROBE_SORTED;
     const int32_t block_cap = sorted ? d.hash_slots : hash_capacity(d.hash_slots);
-    const int32_t wave_cap = sorted ? d.hash_slots / kWavesPerBlock : hash_capacity(d.hash_slots / kWavesPerBlock);
+    int32_t wave_cap = sorted ? d.hash_slots / kWavesPerBlock : hash_capacity(d.hash_slots / kWavesPerBlock);
+    if (tn.wave_outdeg_max > 0 && tn.wave_outdeg_max < wave_cap) wave_cap = tn.wave_outdeg_max;
     Temps tmp{g->ctx->pool.get(), {}};
     const size_t n = (size_t)d.n;
     uint64_t *ka, *kb, *res;
@@ -622,13 +623,12 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
         set_error("schedule: a radix sort pass gave up waiting for an earlier tile");
         return TC_LCC_DEVICE_ERROR;
     }
-    int64_t nb = 0, big = 0;
+    int64_t nb = 0;
     for (int c = 0; c < kClassWave; ++c) {
         nb += (int64_t)hc[c];
-        if (40 - c >= kBigWorkBits) big += (int64_t)hc[c];  // class c holds work of bit length 40 - c
+        d.class_count[c] = (int64_t)hc[c];
     }
     d.n_block = nb;
-    d.n_block_big = big;
     d.n_wave = (int64_t)hc[kClassWave];
     d.n_global = (int64_t)hc[kClassGlobal];
     const int64_t active = nb + d.n_wave + d.n_global;

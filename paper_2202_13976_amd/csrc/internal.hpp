@@ -21,7 +21,7 @@ namespace tcl {
 constexpr int kCountThreads = 256;
 constexpr int kWavesPerBlock = kCountThreads / kWave;
 constexpr int32_t kMaxTableSlots = 4096;  // 4096 x (4 B id + 4 B counter) = 32 KiB per block
-constexpr int kBigWorkBits = 15;          // probes >= 2^14: a vertex the batched launch gives a block
+constexpr int kBigWorkBits = 15;          // default: probes >= 2^14 get a block in the batched launch
 
 int resolve_probe(int probe, int64_t n);
 int32_t table_slots(int probe, int32_t dplus_max);
@@ -82,7 +82,7 @@ struct GraphDev {
     unsigned int* counters = nullptr;      // [8] work-queue counters of the count kernel
     int32_t* vlist = nullptr;   // [n] scheduled vertices: block bin, wave bin, global bin
     int64_t n_block = 0, n_wave = 0, n_global = 0;
-    int64_t n_block_big = 0;    // leading block-class vertices with >= kBigWork probes
+    int64_t class_count[48] = {};  // block-class vertices per work class (class c: bit length 40 - c)
 
     int32_t hash_slots = 64;    // LDS hash slots of one block (power of two)
     int32_t max_dplus = 0;
