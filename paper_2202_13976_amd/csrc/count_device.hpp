@@ -187,46 +187,52 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
         }
         const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
         uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
+        // this lane's tail as a byte offset into adj and a byte length, formed once per chunk
+        // (the tail pointer is adj plus the offset, so loads stay in the global address space)
+        const uint64_t toff = (uint64_t)st * 4u;
+        const uint32_t tbytes = (uint32_t)len * 4u;
 
-        // generator: tail gj (gjv = gj while gj < nk, else -1), next window at gbase;
-        // a spent generator yields windows of tail -1 that read adj[0]
-        const int32_t* tptr = a.adj;
-        int gj = 0, gjv = -1, gbase = 0, glen = 1;
+        // generator (wave-uniform): tail gj (gjv = gj while gj < nk, else -1), next window at
+        // byte gbase4 of the tail, the tail's last candidate at byte glast4; a spent generator
+        // yields windows of tail -1 that read adj[0]
+        const char* tptr = (const char*)a.adj;
+        int gj = 0, gjv = -1;
+        int32_t gbase4 = 0, gend4 = 4;
+        uint32_t glast4 = 0;
         auto fetch_tail = [&]() {
             if (gj < nk) {
-                const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)((uint64_t)st & 0xffffffffu), gj);
-                uint64_t s = lo32;
-                if constexpr (sizeof(OffT) == 8)
-                    s |= (uint64_t)__builtin_amdgcn_readlane((uint32_t)((uint64_t)st >> 32), gj) << 32;
-                tptr = a.adj + s;
-                glen = __builtin_amdgcn_readlane(len, gj);
+                uint64_t off = __builtin_amdgcn_readlane((uint32_t)toff, gj);
+                if constexpr (sizeof(OffT) == 8) off |= (uint64_t)__builtin_amdgcn_readlane((uint32_t)(toff >> 32), gj) << 32;
+                tptr = (const char*)a.adj + off;
+                gend4 = (int32_t)__builtin_amdgcn_readlane(tbytes, gj);
                 gjv = gj;
             } else {
-                tptr = a.adj;
-                glen = 1;
+                tptr = (const char*)a.adj;
+                gend4 = 4;
                 gjv = -1;
             }
+            glast4 = (uint32_t)gend4 - 4u;
         };
         // next window: the next 64 candidates of this tail, else the start of this wave's
         // next tail
         auto advance = [&]() {
-            gbase += kWave;
-            if (gbase >= glen) {
-                gbase = 0;
+            gbase4 += kWave * 4;
+            if (gbase4 >= gend4) {
+                gbase4 = 0;
                 gj += NWAVES;
                 fetch_tail();
             }
         };
         gj = wig;
         fetch_tail();
-        // next window of this wave: its tail j, the number of lanes holding candidates, and
-        // this lane's candidate (lanes past the tail re-read its last one; they are masked by
-        // `lim`); a spent generator yields tail -1
+        // next window of this wave: its tail j, the bytes of candidates from the window on
+        // (lanes with lane4 >= lim hold none), and this lane's candidate (lanes past the tail
+        // re-read its last one); a spent generator yields tail -1
         auto gen = [&](int& j, int& lim) -> int32_t {
             j = gjv;
-            lim = glen - gbase;
-            const uint32_t off4 = min((uint32_t)gbase * 4u + lane4, (uint32_t)(glen - 1) * 4u);
-            const int32_t x = *(const int32_t*)((const char*)tptr + off4);
+            lim = gend4 - gbase4;
+            const uint32_t off4 = min((uint32_t)gbase4 + lane4, glast4);
+            const int32_t x = *(const int32_t*)(tptr + off4);
             advance();
             return x;
         };
@@ -268,7 +274,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                         if (js[sl] >= 0) {
                             // v_bfe takes offset and width modulo 32: bit ii % 32 of the word,
                             // and the bits below it
-                            const bool in_tail = lane < lims[sl];
+                            const bool in_tail = (int32_t)lane4 < lims[sl];
                             const bool set = __builtin_amdgcn_ubfe(wd[q], ii[q], 1u) != 0u;
                             // two ballots of plain compares, combined in scalar registers
                             const unsigned long long H =
@@ -289,7 +295,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                         const int j = js[sl], lim = lims[sl];
                         xs[sl] = gen(js[sl], lims[sl]);
                         if (j >= 0) {
-                            const bool hit = probe_one<MODE>(tb, x, lane < lim);
+                            const bool hit = probe_one<MODE>(tb, x, (int32_t)lane4 < lim);
                             account(j, __builtin_amdgcn_ballot_w64(hit));
                         }
                     }
