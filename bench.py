@@ -204,6 +204,34 @@ def run_timing(ctx, torch, n, src, dst, offset_bytes, tri, lcc, warm: int = 3, l
             "teps": m / (med * 1e-3)}
 
 
+def strategy_timing(ctx, torch, pkg, n, src, dst, offset_bytes, tri, reps: int = 4):
+    """Count-kernel time of each probe strategy on one resident graph (median of `reps` runs
+    after one warm-up; the schedule is rebuilt when the strategy changes), and whether its
+    per-vertex counts equal those of the default strategy."""
+    import numpy as np
+    t0 = ctx.tuning().as_dict()
+    g = ctx.build_csr(n, src, dst, offset_bytes=offset_bytes)
+    out, ref = {}, None
+    try:
+        for name, kw in [("bitmap_or_hash", dict(probe=pkg.PROBE_AUTO)), ("hash", dict(probe=pkg.PROBE_HASH)),
+                         ("sorted_binary_search", dict(probe=pkg.PROBE_SORTED)),
+                         ("hybrid_eq3_merge_path_or_search", dict(probe=pkg.PROBE_MERGE))]:
+            ctx.set_tuning(**kw)
+            g.run(tri, None)
+            ts = []
+            for _ in range(reps):
+                g.run(tri, None)
+                ts.append(g.timings().run_count_ms)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = tri.clone()
+            out[name] = {"count_ms": float(np.median(ts)), "same_counts": bool(torch.equal(ref, tri))}
+    finally:
+        ctx.set_tuning(**t0)
+        g.free()
+    return out
+
+
 def host_cpu():
     model = "unknown"
     try:
@@ -301,6 +329,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-strategies", action="store_true", help="skip the per-probe-strategy count times")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB with an elementwise kernel 3 times (reference for HBM counters)")
     args = ap.parse_args()
@@ -379,6 +408,10 @@ def main():
                   "count_grid": int(info.count_grid), "count_lds_bytes": int(info.count_lds_bytes),
                   "count_blocks_per_cu": int(info.count_blocks_per_cu), "table_slots": int(info.table_slots)},
     }
+    if not args.no_strategies:
+        log("[bench] probe strategies on the resident graph")
+        ctx.set_profiling(True)
+        out["probe_strategies"] = strategy_timing(ctx, torch, pkg, n, src, dst, w["offset_bytes"], tri)
     if not args.no_batch:
         ctx.set_profiling(False)
         out["batch"] = batch_bench(ctx, torch, log)

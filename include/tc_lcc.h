@@ -204,7 +204,9 @@ typedef enum {
     TC_LCC_PROBE_HASH = 1,   /* bucket hash of N+(v) in LDS for every vertex */
     TC_LCC_PROBE_SORTED = 2, /* sorted N+(v) in LDS, binary search per candidate (Sec. II-C1) */
     TC_LCC_PROBE_BITMAP = 3, /* same as AUTO (the bitmap is taken wherever it fits) */
-    TC_LCC_PROBE_MERGE = 4   /* not built: set_tuning returns UNSUPPORTED */
+    TC_LCC_PROBE_MERGE = 4   /* sorted N+(v) in LDS; per in-edge, the rule of Eq. 3 (Sec. III-C)
+                                picks a wave-wide merge path (Alg. 2, SSI) or a binary search
+                                of the shorter list's keys in the longer one (Sec. II-C1) */
 } tc_lcc_probe;
 
 typedef struct {
@@ -213,7 +215,8 @@ typedef struct {
     int64_t wave_work_max;    /* group 0: vertices with at most this many probes go to one wave */
     int32_t wave_outdeg_max;  /* ... and at most this |N+(v)| (0: what a wave's LDS slice holds) */
     int32_t block_threads;    /* threads per count block: 256 (the only value built; 0 = 256) */
-    int32_t merge_ratio_x100; /* reserved for a merge strategy; must be 0 */
+    int32_t merge_ratio_x100; /* PROBE_MERGE: Eq. 3's right side is scaled by this / 100
+                                 (0 = 100, the rule as printed; 0..100000) */
     int32_t batch_grab;       /* batched launch: light vertices a wave takes per queue access
                                  when there are plenty (1..64; 0 = 8) */
     int32_t batch_heavy_bits; /* batched launch: vertices with >= 2^(bits-1) probes get a block

@@ -205,13 +205,10 @@ extern "C" tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* 
         set_error("tc_lcc_set_tuning: null argument");
         return TC_LCC_INVALID_ARGUMENT;
     }
-    if (in->probe == TC_LCC_PROBE_MERGE || in->merge_ratio_x100 != 0) {
-        set_error("tc_lcc_set_tuning: the merge strategy is not built");
-        return TC_LCC_UNSUPPORTED;
-    }
     bool reserved_zero = true;
     for (int32_t r : in->reserved) reserved_zero = reserved_zero && r == 0;
-    if (in->probe < 0 || in->probe > TC_LCC_PROBE_BITMAP || in->group < 0 || in->group > 2 ||
+    if (in->probe < 0 || in->probe > TC_LCC_PROBE_MERGE || in->group < 0 || in->group > 2 ||
+        in->merge_ratio_x100 < 0 || in->merge_ratio_x100 > 100000 ||
         in->wave_work_max < 0 || in->wave_outdeg_max < 0 || (in->block_threads != 0 && in->block_threads != 256) ||
         in->batch_grab < 0 || in->batch_grab > 64 || in->batch_heavy_bits < 0 || in->batch_heavy_bits > 40 ||
         !reserved_zero) {

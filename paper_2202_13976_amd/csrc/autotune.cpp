@@ -1,8 +1,8 @@
 // Autotuner: picks the work-bin boundary, the probe strategy and the batched launch's
 // grab size and heavy threshold by timing candidates on the caller's graphs.
 //
-// The search is coordinate-wise: first the single-graph settings (wave_work_max x probe),
-// then, on top of the best of those, batch_grab, then batch_heavy_bits.  Every candidate's
+// The search is coordinate-wise: first the single-graph settings (wave_work_max x probe,
+// then the hybrid probe of Eq. 3 at the best wave_work_max), then, on top of the best of those, batch_grab, then batch_heavy_bits.  Every candidate's
 // per-vertex counts are compared with those of the setting in force when the call began,
 // so a tuning that changed results would be caught here (results must not depend on it).
 // The chosen setting is installed in the context and can be saved as JSON keyed by the
@@ -121,10 +121,11 @@ tc_lcc_status write_json(const char* path, const std::string& dev, const tc_lcc_
     }
     fprintf(f,
             "{\n \"device\": \"%s\",\n \"tuning\": {\"probe\": %d, \"group\": %d, \"wave_work_max\": %lld, "
-            "\"wave_outdeg_max\": %d, \"block_threads\": %d, \"batch_grab\": %d, \"batch_heavy_bits\": %d},\n"
+            "\"wave_outdeg_max\": %d, \"block_threads\": %d, \"batch_grab\": %d, \"batch_heavy_bits\": %d, "
+            "\"merge_ratio_x100\": %d},\n"
             " \"single_ms\": %.6f,\n \"batch_ms\": %.6f\n}\n",
             dev.c_str(), t.probe, t.group, (long long)t.wave_work_max, t.wave_outdeg_max, t.block_threads,
-            t.batch_grab, t.batch_heavy_bits, single_ms, batch_ms);
+            t.batch_grab, t.batch_heavy_bits, t.merge_ratio_x100, single_ms, batch_ms);
     const bool ok = fclose(f) == 0;
     if (!ok) {
         set_error("tc_lcc_autotune: cannot write %s", path);
@@ -208,6 +209,21 @@ extern "C" tc_lcc_status tc_lcc_autotune(tc_lcc_ctx ctx, int count, const tc_lcc
                     best = t;
                 }
             }
+        // the hybrid of Eq. 3 (merge path or binary search per in-edge) at the best bin boundary
+        {
+            tc_lcc_tuning t = best;
+            t.probe = TC_LCC_PROBE_MERGE;
+            t.merge_ratio_x100 = 0;
+            s = install(ctx, t);
+            if (s != TC_LCC_OK) return s;
+            double ms = 0.0;
+            s = time_single(b, reps, &ms);
+            if (s != TC_LCC_OK) return s;
+            if (ms < best_single) {
+                best_single = ms;
+                best = t;
+            }
+        }
         return install(ctx, best);
     };
     auto batch_pass = [&]() -> tc_lcc_status {
@@ -326,5 +342,7 @@ extern "C" tc_lcc_status tc_lcc_tuning_load(tc_lcc_ctx ctx, const char* json_pat
         else *fd.dst32 = (int32_t)v;
     }
     t.wave_work_max = (int64_t)wwm;
+    // optional: files written before the hybrid probe existed do not have it
+    if (json_int(text, "merge_ratio_x100", &v)) t.merge_ratio_x100 = (int32_t)v;
     return tc_lcc_set_tuning(ctx, &t);
 }

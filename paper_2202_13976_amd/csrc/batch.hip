@@ -79,6 +79,7 @@ __device__ __forceinline__ CountArgs<OffT> batch_args(const BatchGraph& G) {
     a.t = G.t;
     a.ctr = nullptr;
     a.slots = 0;
+    a.merge_x100 = 100;
     return a;
 }
 

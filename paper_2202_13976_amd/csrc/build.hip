@@ -579,9 +579,11 @@ __global__ void k_vlist(const uint64_t* __restrict__ keys, int64_t cnt, int bits
         vlist[i] = (int32_t)(keys[i] & mask);
 }
 
-// LDS slots of one block's table: the sorted list itself, or a hash table for the longest list.
+// LDS slots of one block's table: the sorted list itself (binary search or hybrid), or a hash
+// table for the longest list.
 int32_t table_slots(int probe, int32_t dplus_max) {
-    int32_t need = probe == TC_LCC_PROBE_SORTED ? dplus_max : hash_table_slots(dplus_max);
+    const bool sorted = probe == TC_LCC_PROBE_SORTED || probe == TC_LCC_PROBE_MERGE;
+    int32_t need = sorted ? dplus_max : hash_table_slots(dplus_max);
     // every wave's slice of the table holds at least the 64 slots of the smallest hash table
     int32_t s = 64 * kWavesPerBlock;
     while (s < need && s < kMaxTableSlots) s <<= 1;
@@ -592,7 +594,7 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     GraphDev& d = g->d;
     const int probe = resolve_probe(tn.probe, d.n);
     d.hash_slots = table_slots(probe, d.max_dplus);
-    const bool sorted = probe == TC_LCC_PROBE_SORTED;
+    const bool sorted = probe == TC_LCC_PROBE_SORTED || probe == TC_LCC_PROBE_MERGE;
     const int32_t block_cap = sorted ? d.hash_slots : hash_capacity(d.hash_slots);
     int32_t wave_cap = sorted ? d.hash_slots / kWavesPerBlock : hash_capacity(d.hash_slots / kWavesPerBlock);
     if (tn.wave_outdeg_max > 0 && tn.wave_outdeg_max < wave_cap) wave_cap = tn.wave_outdeg_max;

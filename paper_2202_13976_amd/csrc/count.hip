@@ -134,12 +134,13 @@ __global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
 int resolve_probe(int probe, int64_t n) {
     (void)n;
     if (probe == TC_LCC_PROBE_SORTED) return TC_LCC_PROBE_SORTED;
+    if (probe == TC_LCC_PROBE_MERGE) return TC_LCC_PROBE_MERGE;
     if (probe == TC_LCC_PROBE_HASH) return TC_LCC_PROBE_HASH;
     return TC_LCC_PROBE_AUTO;
 }
 
 template <typename OffT>
-static tc_lcc_status launch_typed(tc_lcc_graph g, int spare_per_cu, hipStream_t st) {
+static tc_lcc_status launch_typed(tc_lcc_graph g, int merge_x100, int spare_per_cu, hipStream_t st) {
     GraphDev& d = g->d;
     CountArgs<OffT> a;
     a.out_off = (const OffT*)d.out_off;
@@ -155,15 +156,17 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, int spare_per_cu, hipStream_t 
     a.t = d.t_rank;
     a.ctr = d.counters;
     a.slots = d.hash_slots;
+    a.merge_x100 = merge_x100 > 0 ? merge_x100 : 100;
     if (d.n_block + d.n_wave > 0) {
         if (d.hash_slots < 64 * kWavesPerBlock || (d.hash_slots & (d.hash_slots - 1)) != 0) {
             set_error("count: table of %d slots cannot be split into %d wave slices", d.hash_slots, kWavesPerBlock);
             return TC_LCC_DEVICE_ERROR;
         }
         const size_t lds = (size_t)d.hash_slots * 8;  // keys and counters
-        auto kern = (d.sched_probe == TC_LCC_PROBE_SORTED) ? k_count<OffT, TC_LCC_PROBE_SORTED>
-                    : (d.sched_probe == TC_LCC_PROBE_HASH) ? k_count<OffT, TC_LCC_PROBE_HASH>
-                                                           : k_count<OffT, TC_LCC_PROBE_AUTO>;
+        auto kern = (d.sched_probe == TC_LCC_PROBE_SORTED)  ? k_count<OffT, TC_LCC_PROBE_SORTED>
+                    : (d.sched_probe == TC_LCC_PROBE_MERGE) ? k_count<OffT, TC_LCC_PROBE_MERGE>
+                    : (d.sched_probe == TC_LCC_PROBE_HASH)  ? k_count<OffT, TC_LCC_PROBE_HASH>
+                                                            : k_count<OffT, TC_LCC_PROBE_AUTO>;
         int per_cu = 0;
         TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kCountThreads, lds));
         if (per_cu - spare_per_cu >= 1) per_cu -= spare_per_cu;
@@ -189,9 +192,8 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, int spare_per_cu, hipStream_t 
 }
 
 tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, int spare_per_cu, hipStream_t st) {
-    (void)tn;
-    return g->d.off_bytes == 4 ? launch_typed<int32_t>(g, spare_per_cu, st)
-                               : launch_typed<int64_t>(g, spare_per_cu, st);
+    return g->d.off_bytes == 4 ? launch_typed<int32_t>(g, tn.merge_ratio_x100, spare_per_cu, st)
+                               : launch_typed<int64_t>(g, tn.merge_ratio_x100, spare_per_cu, st);
 }
 
 // ------------------------------------------------------------------ zeroing and epilogue

@@ -21,7 +21,8 @@ struct CountArgs {
     int64_t n_block, n_wave, n_global;
     unsigned long long* t;
     unsigned int* ctr;
-    int32_t slots;  // table slots of a block (power of two, >= 256)
+    int32_t slots;       // table slots of a block (power of two, >= 256)
+    int32_t merge_x100;  // hybrid probe: scale of Eq. 3's right side, in hundredths
 };
 
 // bucket hash: high bits of a 24x24-bit product (one full-rate multiply)
@@ -92,7 +93,7 @@ struct Win {
 
 // LDS view of the staged N+(v) for one probe method.
 //   hash:   keys[T] (-1 = empty) and cnt[T], 4-slot buckets
-//   sorted: keys[dv] = N+(v) and cnt[dv], binary search
+//   sorted: keys[dv] = N+(v) and cnt[dv], binary search (or the hybrid of Eq. 3)
 //   bitmap: bm[2 (words + 1)]: per 32-rank word of the range (v, vmax] the bits and the
 //           index in N+(v) of the word's first entry, plus one zero guard word; cnt[dv].
 //           The entry index of a hit is first + popcount of the bits below it; candidates
@@ -308,6 +309,119 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
     }
 }
 
+// One entry of a per-lane value as seen from lane j (j wave-uniform).
+template <typename OffT>
+__device__ __forceinline__ OffT lane_value(OffT x, int j) {
+    if constexpr (sizeof(OffT) == 8) {
+        const uint64_t y = (uint64_t)x;
+        return (OffT)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)y, j) |
+                      ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(y >> 32), j) << 32));
+    } else {
+        return (OffT)__builtin_amdgcn_readlane((int32_t)x, j);
+    }
+}
+
+// The paper's hybrid intersection on the sorted N+(v) (keys[dv] in LDS): per in-edge, the
+// tail A of N+(u) after v and B = N+(v) go to the sorted set intersection (Alg. 2) when the
+// rule of Eq. 3 says it is the cheaper one (with s <= l the two lengths, l / s <= log2(l) - 1,
+// its right side scaled by merge_x100 / 100), else to a binary search (Sec. II-C1).
+//   merge: a merge path over the whole wave.  The merged order of A and B (ties: A first) is
+//          cut into 64 equal pieces; lane i finds where its piece starts by a binary search
+//          along its diagonal and merges it.  A pair is counted when its A entry is taken
+//          while the B cursor rests on an equal key, so every common key once.
+//   search: 64 keys of the shorter list at a time, each looked up in the longer one (the
+//          tail is searched in global memory, N+(v) in LDS).
+// Waves of a group take interleaved tails, as in the probe walk.
+template <typename OffT, int NWAVES>
+__device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig,
+                                  unsigned long long& local) {
+    const int lane = lane_id();
+    wig = __builtin_amdgcn_readfirstlane(wig);
+    const int32_t lb = tb.T;
+    const int32_t* B = tb.keys;
+    const float scale = (float)a.merge_x100 * 0.01f;
+    const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
+    for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
+        const OffT k = cb + lane;
+        int32_t u = 0;
+        OffT st = 0;
+        int32_t len = 0;
+        if (k < i1) {
+            u = a.in_u[k];
+            st = a.in_start[k];
+            len = a.in_len[k];
+        }
+        const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
+        for (int j = wig; j < nk; j += NWAVES) {
+            const int32_t tu = lane_value(u, j);
+            const int32_t la = lane_value(len, j);
+            const int32_t* A = a.adj + lane_value(st, j);
+            const int32_t sh = min(la, lb), lg = max(la, lb);
+            const bool merge = sh > 0 && (float)lg <= (float)sh * (__log2f((float)lg) - 1.0f) * scale;
+            uint32_t c = 0;
+            if (merge) {
+                const int32_t L = la + lb;
+                const int32_t per = (L + kWave - 1) / kWave;
+                const int32_t d0 = min(lane * per, L), d1 = min(d0 + per, L);
+                // i = number of A entries among the first d0 of the merged order
+                int32_t lo = max(0, d0 - lb), hi = min(d0, la);
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (A[mid] <= B[d0 - 1 - mid]) lo = mid + 1;
+                    else hi = mid;
+                }
+                int32_t i = lo, jb = d0 - lo;
+                int32_t x = i < la ? A[i] : 0;
+                int32_t y = jb < lb ? B[jb] : 0;
+                for (int32_t s = d0; s < d1; ++s) {
+                    if (i < la && (jb >= lb || x <= y)) {
+                        if (jb < lb && x == y) {
+                            atomicAdd(&tb.cnt[jb], 1u);
+                            ++c;
+                        }
+                        ++i;
+                        if (i < la) x = A[i];
+                    } else {
+                        ++jb;
+                        if (jb < lb) y = B[jb];
+                    }
+                }
+            } else if (la <= lb) {
+                for (int32_t b = 0; b < la; b += kWave) {
+                    const int32_t i = b + lane;
+                    if (i < la) {
+                        const int sl = sorted_find(B, lb, A[i]);
+                        if (sl >= 0) {
+                            atomicAdd(&tb.cnt[sl], 1u);
+                            ++c;
+                        }
+                    }
+                }
+            } else {
+                for (int32_t b = 0; b < lb; b += kWave) {
+                    const int32_t jb = b + lane;
+                    if (jb < lb) {
+                        const int32_t y = B[jb];
+                        int32_t lo = 0, hi = la;
+                        while (lo < hi) {
+                            const int32_t mid = (lo + hi) >> 1;
+                            if (A[mid] < y) lo = mid + 1;
+                            else hi = mid;
+                        }
+                        if (lo < la && A[lo] == y) {
+                            atomicAdd(&tb.cnt[jb], 1u);
+                            ++c;
+                        }
+                    }
+                }
+            }
+            const uint32_t ct = wave_sum(c);
+            if (lane == 0 && ct) atomicAdd(&a.t[tu], (unsigned long long)ct);
+            local += c;
+        }
+    }
+}
+
 // Bytes of the bitmap layout for `words` bitmap words (plus the guard word) and dv counters.
 __host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
     return 8u * (words + 1u) + 4u * (uint32_t)dv;
@@ -316,7 +430,7 @@ __host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_
 // One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
 // wig = wave index in the group) with an LDS region of region_bytes.  The probe method is
 // chosen per vertex: the rank bitmap when it fits (AUTO or BITMAP), else the hash; or the
-// sorted list when asked for.  Returns this lane's share of t(v) in `local`.
+// sorted list (binary search per candidate, or the hybrid of Eq. 3) when asked for.  Returns this lane's share of t(v) in `local`.
 template <typename OffT, int PROBE, int NWAVES>
 __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region, uint32_t region_bytes,
                                int gtid, int wig, unsigned long long& local) {
@@ -328,8 +442,8 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
     Table tb;
     tb.base = v + 1;
     int mode;
-    if constexpr (PROBE == TC_LCC_PROBE_SORTED) {
-        mode = TC_LCC_PROBE_SORTED;
+    if constexpr (PROBE == TC_LCC_PROBE_SORTED || PROBE == TC_LCC_PROBE_MERGE) {
+        mode = PROBE;
     } else {
         tb.span = (uint32_t)(nv[dv - 1] - v);
         tb.words = (tb.span + 31u) >> 5;
@@ -377,6 +491,7 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
     // ---- probe the tails of the in-edges
     if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, v, tb, wig, local);
     else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, v, tb, wig, local);
+    else if (mode == TC_LCC_PROBE_MERGE) walk_tails_hybrid<OffT, NWAVES>(a, v, tb, wig, local);
     else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, v, tb, wig, local);
     group_sync<NWAVES>();
 

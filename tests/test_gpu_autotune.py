@@ -50,7 +50,7 @@ def test_autotune_picks_a_candidate_and_keeps_results(ctx, graphs):
     with tempfile.TemporaryDirectory() as tmp:
         path = os.path.join(tmp, "tuning.json")
         t = ctx.autotune(gs, what=3, reps=2, path=path)
-        assert t.probe in (pkg.PROBE_AUTO, pkg.PROBE_HASH)
+        assert t.probe in (pkg.PROBE_AUTO, pkg.PROBE_HASH, pkg.PROBE_MERGE)
         assert t.wave_work_max in (1024, 2048, 4096, 8192, 16384)
         assert t.batch_grab in (1, 4, 8, 16)
         assert t.batch_heavy_bits in (12, 13, 14, 15, 16, 18)
@@ -87,7 +87,8 @@ def test_autotune_batch_only(ctx, graphs):
 def test_tuning_validation_and_load_errors(ctx, graphs):
     raw, gs = graphs
     default = ctx.tuning().as_dict()
-    for bad, status in [(dict(probe=pkg.PROBE_MERGE), pkg.UNSUPPORTED), (dict(merge_ratio_x100=150), pkg.UNSUPPORTED),
+    for bad, status in [(dict(probe=5), pkg.INVALID_ARGUMENT), (dict(merge_ratio_x100=-1), pkg.INVALID_ARGUMENT),
+                        (dict(merge_ratio_x100=100001), pkg.INVALID_ARGUMENT),
                         (dict(batch_grab=65), pkg.INVALID_ARGUMENT), (dict(batch_heavy_bits=41), pkg.INVALID_ARGUMENT),
                         (dict(block_threads=512), pkg.INVALID_ARGUMENT), (dict(wave_outdeg_max=-1), pkg.INVALID_ARGUMENT),
                         (dict(group=3), pkg.INVALID_ARGUMENT)]:

@@ -107,7 +107,7 @@ def test_rmat_s23_sampled(ctx):
 
 # ------------------------------------------------------------------ strategies (results never depend on them)
 
-@pytest.mark.parametrize("probe", [pkg.PROBE_HASH, pkg.PROBE_SORTED, pkg.PROBE_BITMAP])
+@pytest.mark.parametrize("probe", [pkg.PROBE_HASH, pkg.PROBE_SORTED, pkg.PROBE_BITMAP, pkg.PROBE_MERGE])
 @pytest.mark.parametrize("group,wave_max", [(0, 4096), (0, 0), (0, 1 << 40), (1, 0), (2, 0)])
 def test_strategies(ctx, probe, group, wave_max):
     ctx.set_tuning(probe=probe, group=group, wave_work_max=wave_max)
@@ -117,6 +117,27 @@ def test_strategies(ctx, probe, group, wave_max):
             check(ctx, n, s, d, f"{label} probe={probe} group={group} wave_max={wave_max}", offset_bytes=8)
     finally:
         ctx.set_tuning(probe=pkg.PROBE_AUTO, group=0, wave_work_max=4096)
+
+
+@pytest.mark.parametrize("ratio", [1, 100, 100000])
+def test_hybrid_rule_branches(ctx, ratio):
+    """The hybrid probe (Eq. 3): ratio 1 makes nearly every in-edge a binary search (both
+    directions: tails longer and shorter than N+(v)), 100000 nearly every one a merge path,
+    100 is the rule as printed.  Skewed, dense and uniform graphs, one- and multi-wave
+    vertices."""
+    ctx.set_tuning(probe=pkg.PROBE_MERGE, merge_ratio_x100=ratio)
+    try:
+        hub_s, hub_d = clique(120)
+        star = np.arange(120, 2120, dtype=np.int32)
+        hs = np.concatenate([hub_s, np.repeat(np.arange(0, 40, dtype=np.int32), 50), star[:1000]])
+        hd = np.concatenate([hub_d, star, np.roll(star, 7)[:1000]])
+        for label, (n, s, d) in [("RMAT S14", synth.rmat_scale(14, 16, seed=21)),
+                                 ("ER 2000 dense", (2000, *synth.er(2000, 2000 * 60, seed=22))),
+                                 ("K120 + stars", (2120, hs, hd))]:
+            for ob in (4, 8):
+                check(ctx, n, s, d, f"{label} merge ratio={ratio}", offset_bytes=ob)
+    finally:
+        ctx.set_tuning(probe=pkg.PROBE_AUTO, merge_ratio_x100=0)
 
 
 # ------------------------------------------------------------------ edge cases
@@ -156,15 +177,18 @@ def test_large_clique_global_path(ctx):
     assert bool((tri == (n - 1) * (n - 2) // 2).all())
     assert bool((lcc == 1.0).all())
     g.free()
-    # the same clique with 4-byte offsets and the sorted-list probe (a 4096-key table holds it)
+    # the same clique with 4-byte offsets and the sorted-list probes (a 4096-key table holds
+    # it); the hybrid merges lists of up to 2799 + 2798 entries
     probe0 = ctx.tuning().probe
-    ctx.set_tuning(probe=pkg.PROBE_SORTED)
     try:
-        g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=4)
-        tri, lcc = g.run()
-        torch.cuda.synchronize()
-        assert bool((tri == (n - 1) * (n - 2) // 2).all()) and bool((lcc == 1.0).all())
-        g.free()
+        for probe in (pkg.PROBE_SORTED, pkg.PROBE_MERGE):
+            say(f"[gpu] K{n} probe={probe}")
+            ctx.set_tuning(probe=probe)
+            g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=4)
+            tri, lcc = g.run()
+            torch.cuda.synchronize()
+            assert bool((tri == (n - 1) * (n - 2) // 2).all()) and bool((lcc == 1.0).all())
+            g.free()
     finally:
         ctx.set_tuning(probe=probe0)
 
