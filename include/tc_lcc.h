@@ -221,11 +221,14 @@ typedef struct {
                                  when there are plenty (1..64; 0 = 8) */
     int32_t batch_heavy_bits; /* batched launch: vertices with >= 2^(bits-1) probes get a block
                                  (1..40; 0 = 15) */
-    int32_t reserved[5];      /* must be 0 */
+    int32_t row_sort_max;     /* builder: rows of N+ up to this long are sorted in LDS after a
+                                 sort by source rank (1..4096; 0 = 4096); if a longer row exists,
+                                 the oriented edges get a full radix sort instead */
+    int32_t reserved[4];      /* must be 0 */
 } tc_lcc_tuning;
 
 /* Read or replace the context's tuning.  Results never depend on it.  INVALID_ARGUMENT for
- * values out of range, UNSUPPORTED for the merge strategy. */
+ * values out of range.  A graph keeps the builder settings it was built with. */
 tc_lcc_status tc_lcc_get_tuning(tc_lcc_ctx ctx, tc_lcc_tuning* out);
 tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* in);
 

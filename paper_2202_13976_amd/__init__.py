@@ -57,7 +57,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("probe", ctypes.c_int32), ("group", ctypes.c_int32), ("wave_work_max", ctypes.c_int64),
                 ("wave_outdeg_max", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("merge_ratio_x100", ctypes.c_int32), ("batch_grab", ctypes.c_int32),
-                ("batch_heavy_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("batch_heavy_bits", ctypes.c_int32), ("row_sort_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

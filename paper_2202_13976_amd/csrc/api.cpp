@@ -211,6 +211,7 @@ extern "C" tc_lcc_status tc_lcc_set_tuning(tc_lcc_ctx ctx, const tc_lcc_tuning* 
         in->merge_ratio_x100 < 0 || in->merge_ratio_x100 > 100000 ||
         in->wave_work_max < 0 || in->wave_outdeg_max < 0 || (in->block_threads != 0 && in->block_threads != 256) ||
         in->batch_grab < 0 || in->batch_grab > 64 || in->batch_heavy_bits < 0 || in->batch_heavy_bits > 40 ||
+        in->row_sort_max < 0 || in->row_sort_max > 4096 ||
         !reserved_zero) {
         set_error("tc_lcc_set_tuning: value out of range");
         return TC_LCC_INVALID_ARGUMENT;
@@ -268,9 +269,8 @@ extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_i
         tn = ctx->tuning;
         gen = ctx->tuning_gen;
     }
-    tc_lcc_status s = build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, st, g);
+    tc_lcc_status s = build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, tn, st, g);
     if (s == TC_LCC_OK) {
-        (void)tn;
         g->d.sched_gen = gen;
         if (hipEventCreateWithFlags(&g->last_use, hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(g->last_use, st) != hipSuccess) {

@@ -122,10 +122,10 @@ tc_lcc_status write_json(const char* path, const std::string& dev, const tc_lcc_
     fprintf(f,
             "{\n \"device\": \"%s\",\n \"tuning\": {\"probe\": %d, \"group\": %d, \"wave_work_max\": %lld, "
             "\"wave_outdeg_max\": %d, \"block_threads\": %d, \"batch_grab\": %d, \"batch_heavy_bits\": %d, "
-            "\"merge_ratio_x100\": %d},\n"
+            "\"merge_ratio_x100\": %d, \"row_sort_max\": %d},\n"
             " \"single_ms\": %.6f,\n \"batch_ms\": %.6f\n}\n",
             dev.c_str(), t.probe, t.group, (long long)t.wave_work_max, t.wave_outdeg_max, t.block_threads,
-            t.batch_grab, t.batch_heavy_bits, t.merge_ratio_x100, single_ms, batch_ms);
+            t.batch_grab, t.batch_heavy_bits, t.merge_ratio_x100, t.row_sort_max, single_ms, batch_ms);
     const bool ok = fclose(f) == 0;
     if (!ok) {
         set_error("tc_lcc_autotune: cannot write %s", path);
@@ -342,7 +342,8 @@ extern "C" tc_lcc_status tc_lcc_tuning_load(tc_lcc_ctx ctx, const char* json_pat
         else *fd.dst32 = (int32_t)v;
     }
     t.wave_work_max = (int64_t)wwm;
-    // optional: files written before the hybrid probe existed do not have it
+    // optional: files written before these fields existed do not have them
     if (json_int(text, "merge_ratio_x100", &v)) t.merge_ratio_x100 = (int32_t)v;
+    if (json_int(text, "row_sort_max", &v)) t.row_sort_max = (int32_t)v;
     return tc_lcc_set_tuning(ctx, &t);
 }

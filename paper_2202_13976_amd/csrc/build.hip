@@ -138,66 +138,195 @@ struct LenIn {
     __device__ uint64_t operator()(size_t i) const { return i < n ? (uint64_t)(uint32_t)p[i] : 0ull; }
 };
 
-__global__ void k_split_adj(const uint64_t* __restrict__ ok, size_t m, int bits, int32_t* __restrict__ adj) {
-    const uint64_t mask = (1ull << bits) - 1;
-    GRID_STRIDE(i, m) adj[i] = (int32_t)(ok[i] & mask);
+// ---- rows of the oriented CSR: after the sort by source rank, each row's entries are in
+// the order the relabel wrote them; these kernels sort every row by target rank in place.
+
+constexpr int kRowSortMax = 4096;  // longest row sorted in LDS (one wave, 16 KiB)
+constexpr int kRowWaves = 4;
+
+// ascending bitonic sort of one value per lane across the wave
+__device__ __forceinline__ uint32_t wave_bitonic_sort(uint32_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t y = (uint32_t)__shfl_xor((int)x, j, kWave);
+            // within an ascending run of k lanes the lower lane of a pair keeps the smaller value
+            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+            x = keep_min ? min(x, y) : max(x, y);
+        }
+    }
+    return x;
 }
 
-// oriented edge i = (u -> v) at position i of N+(u): its tail is adj[i+1 .. out_off[u+1]).
-// Kept (it can close a triangle) if the tail is nonempty and N+(v) is nonempty.
+// One wave per 64 consecutive rows; rows of 2..64 entries, each sorted by the whole wave in
+// registers.  Longer rows are left to k_row_sort_long.
 template <typename OffT>
-__global__ void k_kept_flags(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
-                             const int32_t* __restrict__ dplus, uint8_t* __restrict__ flag) {
+__global__ __launch_bounds__(256) void k_row_sort_short(uint64_t* __restrict__ keys, const OffT* __restrict__ out_off,
+                                                        int64_t n, int bits) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const uint64_t mask = (1ull << bits) - 1;
-    GRID_STRIDE(i, m) {
-        const uint64_t x = ok[i];
-        const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
-        flag[i] = ((int64_t)out_off[u + 1] - (int64_t)i - 1 > 0 && dplus[v] > 0) ? 1 : 0;
+    for (int64_t r0 = wave * kWave; r0 < n; r0 += nwaves * kWave) {
+        const int64_t r = r0 + lane;
+        OffT beg = 0;
+        int32_t d = 0;
+        if (r < n) {
+            beg = out_off[r];
+            d = (int32_t)(out_off[r + 1] - beg);
+        }
+        uint64_t todo = __builtin_amdgcn_ballot_w64(d > 1 && d <= kWave);
+        while (todo) {
+            const int j = (int)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const OffT s = lane_value(beg, j);
+            const int32_t dj = __builtin_amdgcn_readlane(d, j);
+            const uint64_t hi = (uint64_t)(r0 + j) << bits;
+            uint32_t x = lane < dj ? (uint32_t)(keys[s + lane] & mask) : 0xffffffffu;
+            x = wave_bitonic_sort(x);
+            if (lane < dj) keys[s + lane] = hi | x;
+        }
     }
 }
 
-struct U8In {
-    const uint8_t* p;
-    size_t n;
-    __device__ uint32_t operator()(size_t i) const { return i < n ? (uint32_t)p[i] : 0u; }
+// Ascending bitonic sort of buf[0, P) in a wave's LDS slice.  Each stage reads a batch of
+// this lane's pairs before writing any of them, so the reads of a batch are in flight together.
+template <int P>
+__device__ void lds_bitonic(uint32_t* buf) {
+    constexpr int kPairs = P / 2 / kWave;  // compare-exchange pairs per lane and stage
+    constexpr int kBatch = kPairs < 8 ? kPairs : 8;
+    const int lane = lane_id();
+#pragma unroll 1
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll 1
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+#pragma unroll 1
+            for (int q0 = 0; q0 < kPairs; q0 += kBatch) {
+                uint32_t va[kBatch], vb[kBatch];
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int t = lane + (q0 + q) * kWave;
+                    const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));  // pair (i, i + jj), i & jj == 0
+                    va[q] = buf[i];
+                    vb[q] = buf[i + jj];
+                }
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) {
+                    const int t = lane + (q0 + q) * kWave;
+                    const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+                    const bool up = (i & k) == 0;
+                    const uint32_t lo = min(va[q], vb[q]), hi = max(va[q], vb[q]);
+                    buf[i] = up ? lo : hi;
+                    buf[i + jj] = up ? hi : lo;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// Rows of 65..kRowSortMax entries, listed in `rows`: one wave per row, bitonic sort in the
+// wave's LDS slice over the row padded to a power of two.
+template <typename OffT>
+__global__ __launch_bounds__(kRowWaves * kWave) void k_row_sort_long(uint64_t* __restrict__ keys,
+                                                                     const OffT* __restrict__ out_off,
+                                                                     const int32_t* __restrict__ rows,
+                                                                     int64_t count, int bits) {
+    __shared__ uint32_t lds[kRowWaves][kRowSortMax];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    uint32_t* buf = lds[w];
+    const uint64_t mask = (1ull << bits) - 1;
+    for (int64_t it = (int64_t)blockIdx.x * kRowWaves + w; it < count; it += (int64_t)gridDim.x * kRowWaves) {
+        const int32_t r = rows[it];
+        const OffT s = out_off[r];
+        const int32_t d = (int32_t)(out_off[r + 1] - s);
+        const uint64_t hi = (uint64_t)r << bits;
+        int P = kWave * 2;
+        while (P < d) P <<= 1;
+        for (int i = lane; i < P; i += kWave) buf[i] = i < d ? (uint32_t)(keys[s + i] & mask) : 0xffffffffu;
+        wave_lds_sync();
+        switch (P) {
+            case 128: lds_bitonic<128>(buf); break;
+            case 256: lds_bitonic<256>(buf); break;
+            case 512: lds_bitonic<512>(buf); break;
+            case 1024: lds_bitonic<1024>(buf); break;
+            case 2048: lds_bitonic<2048>(buf); break;
+            default: lds_bitonic<kRowSortMax>(buf); break;
+        }
+        for (int i = lane; i < d; i += kWave) keys[s + i] = hi | buf[i];
+        wave_lds_sync();
+    }
+}
+
+// rows of more than 64 entries (flag for the scan that lists them)
+struct LongRow {
+    const int32_t* dplus;
+    int64_t n;
+    __device__ uint32_t operator()(size_t i) const { return ((int64_t)i < n && dplus[i] > kWave) ? 1u : 0u; }
 };
 
-// What the reverse lists need of kept in-edge p: u, the tail's start in adj and its length.
-struct KeptEdge {
+__global__ void k_list_rows(const int32_t* __restrict__ dplus, int64_t n, const uint32_t* __restrict__ pos,
+                            int32_t* __restrict__ rows) {
+    GRID_STRIDE(r, n) if (dplus[r] > kWave) rows[pos[r]] = (int32_t)r;
+}
+
+__global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int* __restrict__ out) {
+    int mx = 0;
+    GRID_STRIDE(i, n) mx = max(mx, x[i]);
+    for (int d = kWave / 2; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d, kWave));
+    if (lane_id() == 0) atomicMax(out, mx);
+}
+
+// What the reverse lists need of oriented edge i = (u -> v), besides its tail start i + 1:
+// u and the tail length.
+struct EdgePay {
     int32_t u;
     int32_t len;
-    uint64_t start;
 };
 
-// Kept edge i gets kept index p = pos[i]: its sort word (v, p) and its payload, both written
-// in edge order (so sequentially); the sort by v then permutes only the words.
+// Per oriented edge i = (u -> v) at position i of N+(u) (its tail is adj[i+1 .. out_off[u+1])):
+// the adjacency entry, the payload, and the word (v, i) by which the in-edges are sorted.
+// An edge that cannot close a triangle (empty tail, or N+(v) empty) gets the key 2^bits,
+// above every vertex, so it sorts after all in-edges that are kept.
 template <typename OffT>
-__global__ void k_kept_emit(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
-                            const uint8_t* __restrict__ flag, const uint32_t* __restrict__ pos,
-                            uint64_t* __restrict__ words, KeptEdge* __restrict__ pay) {
+__global__ void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
+                            const int32_t* __restrict__ dplus, int32_t* __restrict__ adj,
+                            uint64_t* __restrict__ words, EdgePay* __restrict__ pay) {
     const uint64_t mask = (1ull << bits) - 1;
     GRID_STRIDE(i, m) {
-        if (!flag[i]) continue;
         const uint64_t x = ok[i];
         const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
-        const uint32_t p = pos[i];
-        words[p] = ((uint64_t)v << 32) | (uint64_t)p;
-        KeptEdge e;
-        e.u = (int32_t)u;
-        e.len = (int32_t)((int64_t)out_off[u + 1] - (int64_t)i - 1);
-        e.start = (uint64_t)i + 1;
-        pay[p] = e;
+        adj[i] = (int32_t)v;
+        const int64_t len = (int64_t)out_off[u + 1] - (int64_t)i - 1;
+        const bool kept = len > 0 && dplus[v] > 0;
+        words[i] = ((kept ? (uint64_t)v : (1ull << bits)) << 32) | (uint64_t)i;
+        pay[i] = EdgePay{(int32_t)u, (int32_t)len};
     }
 }
 
-// in-edge k (sorted by v, then by kept index, so by u): one gather of its payload
+// Number of leading words whose key is below 2^bits (the kept in-edges), by bisection.
+__global__ void k_count_kept(const uint64_t* __restrict__ words, size_t m, int bits, uint32_t* __restrict__ out) {
+    const uint64_t cut = (1ull << bits) << 32;
+    size_t lo = 0, hi = m;
+    while (lo < hi) {
+        const size_t mid = (lo + hi) >> 1;
+        if (words[mid] < cut) lo = mid + 1;
+        else hi = mid;
+    }
+    *out = (uint32_t)lo;
+}
+
+// in-edge k (sorted by v, then by edge index, so by u): its edge index is the word's low half
 template <typename OffT>
-__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const KeptEdge* __restrict__ pay,
+__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const EdgePay* __restrict__ pay,
                           int32_t* __restrict__ in_u, OffT* __restrict__ in_start, int32_t* __restrict__ in_len) {
     GRID_STRIDE(k, kept) {
-        const KeptEdge e = pay[words[k] & 0xffffffffull];
+        const uint32_t i = (uint32_t)(words[k] & 0xffffffffull);
+        const EdgePay e = pay[i];
         in_u[k] = e.u;
-        in_start[k] = (OffT)e.start;
+        in_start[k] = (OffT)i + 1;
         in_len[k] = e.len;
     }
 }
@@ -325,7 +454,7 @@ hipError_t run_bounds(G g, size_t N, uint32_t* first, uint32_t* last, int64_t n,
 
 template <typename OffT>
 tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
-                          int on_device, hipStream_t st, tc_lcc_graph g) {
+                          int on_device, int row_max, hipStream_t st, tc_lcc_graph g) {
     GraphDev& d = g->d;
     Temps tmp{ctx->pool.get(), {}};
     const int bits = std::max(1, ceil_log2((uint64_t)n));
@@ -428,7 +557,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     }
 
     mark(d, 2, st);
-    // 3. relabel + orient, sort, oriented CSR
+    // 3. relabel + orient, sort by source rank, oriented CSR; then each row by target rank
     uint64_t* okeys = spare;
     uint64_t* osorted = okeys;
     TCL_TRY(keep(g, N, &d.dplus));
@@ -439,15 +568,46 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     if (m > 0) {
         k_relabel<<<grid_for(m, kB, 8192), kB, 0, st>>>(ukeys, m, bits, rank, okeys);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(okeys, kc, m, 0, 2 * bits, sort_scratch, sort_err, st, &osorted));
+        TCL_HIP(radix_sort_u64(okeys, kc, m, bits, bits, sort_scratch, sort_err, st, &osorted));
     }
     TCL_HIP(run_bounds(GroupShift{osorted, bits}, m, f1, l1, n, st));
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, n, d.dplus);
     TCL_HIP(hipGetLastError());
     TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{d.dplus, n}, N + 1, out_off, scanO, st));
     if (m > 0) {
-        k_split_adj<<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, d.adj);
+        int* mx = bad + 4;
+        k_max_i32<<<grid_for(N, kB, 1024), kB, 0, st>>>(d.dplus, n, mx);
         TCL_HIP(hipGetLastError());
+        // the rows longer than a wave, listed (rpos: scan of their flags)
+        uint32_t* rpos;
+        TCL_TRY(tmp.get(N + 1, &rpos));
+        TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n}, N + 1, rpos, scan32, st));
+        int dmax = 0;
+        uint32_t nlong = 0;
+        TCL_HIP(hipMemcpyAsync(&dmax, mx, sizeof(int), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipMemcpyAsync(&nlong, rpos + N, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipStreamSynchronize(st));
+        if (dmax <= row_max) {
+            const size_t groups = (N + kWave - 1) / kWave;
+            k_row_sort_short<OffT><<<grid_for(groups * kWave, kB, 8192), kB, 0, st>>>(osorted, out_off, n, bits);
+            TCL_HIP(hipGetLastError());
+            if (nlong > 0) {
+                int32_t* rows;
+                TCL_TRY(tmp.get(nlong, &rows));
+                k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, rpos, rows);
+                TCL_HIP(hipGetLastError());
+                k_row_sort_long<OffT><<<grid_for(nlong, kRowWaves, 4096), kRowWaves * kWave, 0, st>>>(
+                    osorted, out_off, rows, (int64_t)nlong, bits);
+                TCL_HIP(hipGetLastError());
+            }
+        } else {
+            // a row too long for the LDS sort: sort the keys by (source, target) in full instead
+            // (an LSD sort over all digits, whatever order the keys are in)
+            uint64_t* full = osorted;
+            TCL_HIP(radix_sort_u64(osorted, osorted == kc ? okeys : kc, m, 0, 2 * bits, sort_scratch, sort_err, st,
+                                   &full));
+            osorted = full;
+        }
     }
 
     mark(d, 3, st);
@@ -457,18 +617,18 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     for (uint64_t* b : {ka, kb, kc})
         if (b != osorted) (wa ? wb : wa) = b;
     uint32_t kept = 0;
-    KeptEdge* pay = nullptr;
+    EdgePay* pay = nullptr;
+    uint64_t* ws = wa;
+    TCL_TRY(tmp.get(std::max<size_t>(m, 1), &pay));
     if (m > 0) {
-        uint8_t* flag;
-        TCL_TRY(tmp.get(m, &flag));
-        k_kept_flags<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, flag);
+        k_edge_emit<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, d.adj, wa, pay);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(exclusive_scan<uint32_t>(U8In{flag, m}, m + 1, pos, scan32, st));
-        TCL_HIP(hipMemcpyAsync(&kept, pos + m, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(radix_sort_u64(wa, wb, m, 32, bits + 1, sort_scratch, sort_err, st, &ws));
+        uint32_t* kc_dev = (uint32_t*)(bad + 5);
+        k_count_kept<<<1, 1, 0, st>>>(ws, m, bits, kc_dev);
+        TCL_HIP(hipGetLastError());
+        TCL_HIP(hipMemcpyAsync(&kept, kc_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipStreamSynchronize(st));
-        TCL_TRY(tmp.get(std::max<size_t>(kept, 1), &pay));
-        k_kept_emit<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, flag, pos, wa, pay);
-        TCL_HIP(hipGetLastError());
     }
     d.m_in_kept = (int64_t)kept;
     const size_t KE = std::max<size_t>((size_t)kept, 1);
@@ -481,8 +641,6 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_TRY(keep(g, N + 1, &in_off));
     d.in_off = in_off;
     TCL_TRY(keep(g, N, &d.work));
-    uint64_t* ws = wa;
-    if (kept > 0) TCL_HIP(radix_sort_u64(wa, wb, kept, 32, bits, sort_scratch, sort_err, st, &ws));
     TCL_HIP(run_bounds(GroupShift{ws, 32}, kept, f2, l2, n, st));
     int32_t* din = deg;  // degrees by vertex are not needed any more (deg_r keeps them by rank)
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f2, l2, n, din);
@@ -527,15 +685,16 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
 }  // namespace
 
 tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
-                          int on_device, int offset_bytes, hipStream_t st, tc_lcc_graph g) {
+                          int on_device, int offset_bytes, const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g) {
     // offsets index the m oriented edges; m <= m_in, so 4 bytes suffice when m_in < 2^31
     int ob = offset_bytes;
     if (ob == 0) ob = (m_in < (1ll << 31)) ? 4 : 8;
     g->d.off_bytes = ob;
-    tc_lcc_status s = (ob == 4) ? build_typed<int32_t>(ctx, n, m_in, src, dst, on_device, st, g)
-                                : build_typed<int64_t>(ctx, n, m_in, src, dst, on_device, st, g);
+    const int row_max = tn.row_sort_max > 0 ? std::min(tn.row_sort_max, kRowSortMax) : kRowSortMax;
+    tc_lcc_status s = (ob == 4) ? build_typed<int32_t>(ctx, n, m_in, src, dst, on_device, row_max, st, g)
+                                : build_typed<int64_t>(ctx, n, m_in, src, dst, on_device, row_max, st, g);
     if (s != TC_LCC_OK) return s;
-    s = build_schedule(g, ctx->tuning, st);
+    s = build_schedule(g, tn, st);
     mark(g->d, 5, st);
     return s;
 }

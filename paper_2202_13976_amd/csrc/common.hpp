@@ -55,6 +55,18 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One entry of a per-lane value as seen from lane j (j wave-uniform).
+template <typename OffT>
+__device__ __forceinline__ OffT lane_value(OffT x, int j) {
+    if constexpr (sizeof(OffT) == 8) {
+        const uint64_t y = (uint64_t)x;
+        return (OffT)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)y, j) |
+                      ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(y >> 32), j) << 32));
+    } else {
+        return (OffT)__builtin_amdgcn_readlane((int32_t)x, j);
+    }
+}
+
 __device__ __forceinline__ unsigned long long lanemask_lt() {
     const int lane = lane_id();
     return lane == 0 ? 0ull : (~0ull >> (kWave - lane));

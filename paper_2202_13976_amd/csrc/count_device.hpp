@@ -309,18 +309,6 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
     }
 }
 
-// One entry of a per-lane value as seen from lane j (j wave-uniform).
-template <typename OffT>
-__device__ __forceinline__ OffT lane_value(OffT x, int j) {
-    if constexpr (sizeof(OffT) == 8) {
-        const uint64_t y = (uint64_t)x;
-        return (OffT)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)y, j) |
-                      ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(y >> 32), j) << 32));
-    } else {
-        return (OffT)__builtin_amdgcn_readlane((int32_t)x, j);
-    }
-}
-
 // The paper's hybrid intersection on the sorted N+(v) (keys[dv] in LDS): per in-edge, the
 // tail A of N+(u) after v and B = N+(v) go to the sorted set intersection (Alg. 2) when the
 // rule of Eq. 3 says it is the cheaper one (with s <= l the two lengths, l / s <= log2(l) - 1,

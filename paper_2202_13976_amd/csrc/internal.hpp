@@ -138,7 +138,7 @@ hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, i
 // build.hip
 tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
                           const int32_t* dst, int inputs_on_device, int offset_bytes,
-                          hipStream_t st, tc_lcc_graph g);
+                          const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g);
 tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
 
 // count.hip

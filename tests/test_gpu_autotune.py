@@ -89,6 +89,7 @@ def test_tuning_validation_and_load_errors(ctx, graphs):
     default = ctx.tuning().as_dict()
     for bad, status in [(dict(probe=5), pkg.INVALID_ARGUMENT), (dict(merge_ratio_x100=-1), pkg.INVALID_ARGUMENT),
                         (dict(merge_ratio_x100=100001), pkg.INVALID_ARGUMENT),
+                        (dict(row_sort_max=4097), pkg.INVALID_ARGUMENT), (dict(row_sort_max=-1), pkg.INVALID_ARGUMENT),
                         (dict(batch_grab=65), pkg.INVALID_ARGUMENT), (dict(batch_heavy_bits=41), pkg.INVALID_ARGUMENT),
                         (dict(block_threads=512), pkg.INVALID_ARGUMENT), (dict(wave_outdeg_max=-1), pkg.INVALID_ARGUMENT),
                         (dict(group=3), pkg.INVALID_ARGUMENT)]:

@@ -222,12 +222,21 @@ def test_invalid_inputs(ctx):
         ctx.build_csr(5, neg, neg)
 
 
-def test_builder_structure(ctx):
-    """The exported CSR: degrees, rank order by (degree, id), orientation and sorted lists."""
+@pytest.mark.parametrize("row_sort_max", [0, 1])
+def test_builder_structure(ctx, row_sort_max):
+    """The exported CSR: degrees, rank order by (degree, id), orientation and sorted lists,
+    and the number of kept in-edges.  row_sort_max 0 sorts rows in LDS after the sort by
+    source (rows of 2..64 and of 65..4096 entries take different kernels); 1 sends the
+    oriented edges through the full radix sort instead."""
     n, s, d = synth.rmat_scale(14, 16, seed=3)
     g_ref = oracle.csr(n, s, d)
-    say("[gpu] builder structure RMAT S14")
-    g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    say(f"[gpu] builder structure RMAT S14 row_sort_max={row_sort_max}")
+    t0 = ctx.tuning().row_sort_max
+    ctx.set_tuning(row_sort_max=row_sort_max)
+    try:
+        g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    finally:
+        ctx.set_tuning(row_sort_max=t0)
     deg, order, off, adj = g.export()
     info = g.info()
     g.free()
@@ -246,3 +255,8 @@ def test_builder_structure(ctx):
     want = np.sort(rows[keep].astype(np.int64) * n + g_ref.adj[keep])
     np.testing.assert_array_equal(got, want)
     assert info.max_out_degree == int(np.diff(off).max())
+    assert info.max_out_degree > 64, "the workload must have rows for the LDS row sort"
+    # kept in-edges: oriented edges with a nonempty tail whose target has a nonempty N+
+    dplus = np.diff(off)
+    tail = off[src + 1] - np.arange(len(adj)) - 1
+    assert info.kept_in_edges == int(np.count_nonzero((tail > 0) & (dplus[adj] > 0)))
