@@ -144,31 +144,75 @@ struct LenIn {
 constexpr int kRowSortMax = 4096;  // longest row sorted in LDS (one wave, 16 KiB)
 constexpr int kRowWaves = 4;
 
-// ascending bitonic sort of one value per lane across the wave
-__device__ __forceinline__ uint32_t wave_bitonic_sort(uint32_t x) {
+// Ascending bitonic sort of one value per lane within each group of G lanes (G a power of two
+// up to 64): the usual network, with every group's last merge ascending.
+template <int G>
+__device__ __forceinline__ uint32_t group_bitonic_sort(uint32_t x) {
     const int lane = lane_id();
 #pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
+    for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             const uint32_t y = (uint32_t)__shfl_xor((int)x, j, kWave);
             // within an ascending run of k lanes the lower lane of a pair keeps the smaller value
-            const bool keep_min = ((lane & k) == 0) == ((lane & j) == 0);
+            const bool up = (k == G) || ((lane & k) == 0);
+            const bool keep_min = up == ((lane & j) == 0);
             x = keep_min ? min(x, y) : max(x, y);
         }
     }
     return x;
 }
 
-// One wave per 64 consecutive rows; rows of 2..64 entries, each sorted by the whole wave in
-// registers.  Longer rows are left to k_row_sort_long.
+template <typename OffT>
+__device__ __forceinline__ OffT shfl_off(OffT x, int src) {
+    if constexpr (sizeof(OffT) == 8) {
+        const uint64_t y = (uint64_t)x;
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)y, src, kWave);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(y >> 32), src, kWave);
+        return (OffT)(((uint64_t)hi << 32) | lo);
+    } else {
+        return (OffT)__shfl((int)x, src, kWave);
+    }
+}
+
+// The rows of `todo` (bits = lanes of the 64-row group starting at r0; lane j holds row
+// r0 + j's start and length), each of at most G entries: 64 / G rows at a time, one per group
+// of G lanes.
+template <int G, typename OffT>
+__device__ __forceinline__ void sort_rows_by_group(uint64_t* __restrict__ keys, uint64_t todo, OffT beg, int32_t d,
+                                                   int64_t r0, int bits) {
+    constexpr int R = kWave / G;
+    const int lane = lane_id(), grp = lane / G, e = lane % G;
+    const uint64_t mask = (1ull << bits) - 1;
+    while (todo) {
+        int js[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            js[q] = todo ? (int)__builtin_ctzll(todo) : -1;
+            todo &= todo - 1;  // no-op once empty
+        }
+        int jg = js[0];
+#pragma unroll
+        for (int q = 1; q < R; ++q) jg = grp == q ? js[q] : jg;
+        const int jl = jg >= 0 ? jg : 0;
+        const OffT s = shfl_off(beg, jl);
+        const int32_t dj = __shfl(d, jl, kWave);
+        const bool valid = jg >= 0 && e < dj;
+        uint32_t x = valid ? (uint32_t)(keys[s + e] & mask) : 0xffffffffu;
+        x = group_bitonic_sort<G>(x);
+        if (valid) keys[s + e] = ((uint64_t)(r0 + jl) << bits) | x;
+    }
+}
+
+// One wave per 64 consecutive rows; rows of 2..64 entries, sorted in registers: rows of up to
+// 16 entries four at a time, up to 32 two at a time, longer ones by the whole wave.  Longer rows
+// are left to k_row_sort_long.
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_row_sort_short(uint64_t* __restrict__ keys, const OffT* __restrict__ out_off,
                                                         int64_t n, int bits) {
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    const uint64_t mask = (1ull << bits) - 1;
     for (int64_t r0 = wave * kWave; r0 < n; r0 += nwaves * kWave) {
         const int64_t r = r0 + lane;
         OffT beg = 0;
@@ -177,17 +221,9 @@ __global__ __launch_bounds__(256) void k_row_sort_short(uint64_t* __restrict__ k
             beg = out_off[r];
             d = (int32_t)(out_off[r + 1] - beg);
         }
-        uint64_t todo = __builtin_amdgcn_ballot_w64(d > 1 && d <= kWave);
-        while (todo) {
-            const int j = (int)__builtin_ctzll(todo);
-            todo &= todo - 1;
-            const OffT s = lane_value(beg, j);
-            const int32_t dj = __builtin_amdgcn_readlane(d, j);
-            const uint64_t hi = (uint64_t)(r0 + j) << bits;
-            uint32_t x = lane < dj ? (uint32_t)(keys[s + lane] & mask) : 0xffffffffu;
-            x = wave_bitonic_sort(x);
-            if (lane < dj) keys[s + lane] = hi | x;
-        }
+        sort_rows_by_group<16>(keys, __builtin_amdgcn_ballot_w64(d > 1 && d <= 16), beg, d, r0, bits);
+        sort_rows_by_group<32>(keys, __builtin_amdgcn_ballot_w64(d > 16 && d <= 32), beg, d, r0, bits);
+        sort_rows_by_group<64>(keys, __builtin_amdgcn_ballot_w64(d > 32 && d <= kWave), beg, d, r0, bits);
     }
 }
 
