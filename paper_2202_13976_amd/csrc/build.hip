@@ -142,7 +142,6 @@ struct LenIn {
 // the order the relabel wrote them; these kernels sort every row by target rank in place.
 
 constexpr int kRowSortMax = 4096;  // longest row sorted in LDS (one wave, 16 KiB)
-constexpr int kRowWaves = 4;
 
 // Ascending bitonic sort of one value per lane within each group of G lanes (G a power of two
 // up to 64): the usual network, with every group's last merge ascending.
@@ -227,72 +226,94 @@ __global__ __launch_bounds__(256) void k_row_sort_short(uint64_t* __restrict__ k
     }
 }
 
-// Ascending bitonic sort of buf[0, P) in a wave's LDS slice.  Each stage reads a batch of
-// this lane's pairs before writing any of them, so the reads of a batch are in flight together.
-template <int P>
-__device__ void lds_bitonic(uint32_t* buf) {
-    constexpr int kPairs = P / 2 / kWave;  // compare-exchange pairs per lane and stage
-    constexpr int kBatch = kPairs < 8 ? kPairs : 8;
-    const int lane = lane_id();
-#pragma unroll 1
-    for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll 1
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-#pragma unroll 1
-            for (int q0 = 0; q0 < kPairs; q0 += kBatch) {
-                uint32_t va[kBatch], vb[kBatch];
+// Ascending bitonic sort of 64·E values held E per lane, element e of lane l being entry
+// 64·e + l.  Steps between entries 64 or more apart are compare-exchanges between a lane's own
+// registers; shorter ones exchange with lane l ^ j.
+template <int E, int JE>
+__device__ __forceinline__ void reg_step(uint32_t (&v)[E], int k) {
 #pragma unroll
-                for (int q = 0; q < kBatch; ++q) {
-                    const int t = lane + (q0 + q) * kWave;
-                    const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));  // pair (i, i + jj), i & jj == 0
-                    va[q] = buf[i];
-                    vb[q] = buf[i + jj];
-                }
-#pragma unroll
-                for (int q = 0; q < kBatch; ++q) {
-                    const int t = lane + (q0 + q) * kWave;
-                    const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
-                    const bool up = (i & k) == 0;
-                    const uint32_t lo = min(va[q], vb[q]), hi = max(va[q], vb[q]);
-                    buf[i] = up ? lo : hi;
-                    buf[i + jj] = up ? hi : lo;
-                }
-            }
-            wave_lds_sync();
+    for (int e = 0; e < E; ++e) {
+        if ((e & JE) == 0) {
+            const int f = e | JE;
+            const bool up = ((e << 6) & k) == 0;  // entry 64·e + l: bit k is in e, as k >= 128
+            const uint32_t lo = min(v[e], v[f]), hi = max(v[e], v[f]);
+            v[e] = up ? lo : hi;
+            v[f] = up ? hi : lo;
         }
     }
 }
 
-// Rows of 65..kRowSortMax entries, listed in `rows`: one wave per row, bitonic sort in the
-// wave's LDS slice over the row padded to a power of two.
-template <typename OffT>
-__global__ __launch_bounds__(kRowWaves * kWave) void k_row_sort_long(uint64_t* __restrict__ keys,
-                                                                     const OffT* __restrict__ out_off,
-                                                                     const int32_t* __restrict__ rows,
-                                                                     int64_t count, int bits) {
-    __shared__ uint32_t lds[kRowWaves][kRowSortMax];
-    const int lane = lane_id(), w = threadIdx.x / kWave;
-    uint32_t* buf = lds[w];
+template <int E>
+__device__ void reg_bitonic(uint32_t (&v)[E]) {
+    const int lane = lane_id();
+#pragma unroll 1
+    for (int k = 2; k <= kWave * E; k <<= 1) {
+#pragma unroll 1
+        for (int j = k >> 1; j >= kWave; j >>= 1) {
+            switch (j / kWave) {
+                case 1: if constexpr (E > 1) reg_step<E, 1>(v, k); break;
+                case 2: if constexpr (E > 2) reg_step<E, 2>(v, k); break;
+                case 4: if constexpr (E > 4) reg_step<E, 4>(v, k); break;
+                case 8: if constexpr (E > 8) reg_step<E, 8>(v, k); break;
+                case 16: if constexpr (E > 16) reg_step<E, 16>(v, k); break;
+                default: if constexpr (E > 32) reg_step<E, 32>(v, k); break;
+            }
+        }
+#pragma unroll 1
+        for (int j = min(k >> 1, kWave / 2); j > 0; j >>= 1) {
+            const bool lower = (lane & j) == 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint32_t y = (uint32_t)__shfl_xor((int)v[e], j, kWave);
+                const bool up = (((e << 6) | lane) & k) == 0;
+                v[e] = (up == lower) ? min(v[e], y) : max(v[e], y);
+            }
+        }
+    }
+}
+
+template <int E, typename OffT>
+__device__ __forceinline__ void sort_long_row(uint64_t* __restrict__ keys, OffT s, int32_t d, uint64_t hi,
+                                              uint64_t mask) {
+    const int lane = lane_id();
+    uint32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * kWave + lane;
+        v[e] = i < d ? (uint32_t)(keys[s + i] & mask) : 0xffffffffu;
+    }
+    reg_bitonic<E>(v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * kWave + lane;
+        if (i < d) keys[s + i] = hi | v[e];
+    }
+}
+
+// Rows listed in `rows` with LO < length <= HI (65 <= LO, HI <= kRowSortMax): one wave per row,
+// sorted in registers over the row padded to a power of two.  Two launches split the lengths
+// at 1024, so the register budget of the longest rows does not limit the many shorter ones.
+template <typename OffT, int LO, int HI>
+__global__ __launch_bounds__(256) void k_row_sort_long(uint64_t* __restrict__ keys, const OffT* __restrict__ out_off,
+                                                       const int32_t* __restrict__ rows, int64_t count, int bits) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     const uint64_t mask = (1ull << bits) - 1;
-    for (int64_t it = (int64_t)blockIdx.x * kRowWaves + w; it < count; it += (int64_t)gridDim.x * kRowWaves) {
+    for (int64_t it = wave; it < count; it += nwaves) {
         const int32_t r = rows[it];
         const OffT s = out_off[r];
         const int32_t d = (int32_t)(out_off[r + 1] - s);
+        if (d <= LO || d > HI) continue;
         const uint64_t hi = (uint64_t)r << bits;
-        int P = kWave * 2;
-        while (P < d) P <<= 1;
-        for (int i = lane; i < P; i += kWave) buf[i] = i < d ? (uint32_t)(keys[s + i] & mask) : 0xffffffffu;
-        wave_lds_sync();
-        switch (P) {
-            case 128: lds_bitonic<128>(buf); break;
-            case 256: lds_bitonic<256>(buf); break;
-            case 512: lds_bitonic<512>(buf); break;
-            case 1024: lds_bitonic<1024>(buf); break;
-            case 2048: lds_bitonic<2048>(buf); break;
-            default: lds_bitonic<kRowSortMax>(buf); break;
+        if constexpr (HI <= 1024) {
+            if (d <= 128) sort_long_row<2>(keys, s, d, hi, mask);
+            else if (d <= 256) sort_long_row<4>(keys, s, d, hi, mask);
+            else if (d <= 512) sort_long_row<8>(keys, s, d, hi, mask);
+            else sort_long_row<16>(keys, s, d, hi, mask);
+        } else {
+            if (d <= 2048) sort_long_row<32>(keys, s, d, hi, mask);
+            else sort_long_row<64>(keys, s, d, hi, mask);
         }
-        for (int i = lane; i < d; i += kWave) keys[s + i] = hi | buf[i];
-        wave_lds_sync();
     }
 }
 
@@ -632,9 +653,14 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
                 TCL_TRY(tmp.get(nlong, &rows));
                 k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, rpos, rows);
                 TCL_HIP(hipGetLastError());
-                k_row_sort_long<OffT><<<grid_for(nlong, kRowWaves, 4096), kRowWaves * kWave, 0, st>>>(
+                k_row_sort_long<OffT, kWave, 1024><<<grid_for((size_t)nlong * kWave, kB, 8192), kB, 0, st>>>(
                     osorted, out_off, rows, (int64_t)nlong, bits);
                 TCL_HIP(hipGetLastError());
+                if (dmax > 1024) {
+                    k_row_sort_long<OffT, 1024, kRowSortMax><<<grid_for((size_t)nlong * kWave, kB, 1024), kB, 0, st>>>(
+                        osorted, out_off, rows, (int64_t)nlong, bits);
+                    TCL_HIP(hipGetLastError());
+                }
             }
         } else {
             // a row too long for the LDS sort: sort the keys by (source, target) in full instead
