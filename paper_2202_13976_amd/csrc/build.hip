@@ -55,16 +55,16 @@ struct UniqueFlag {
     }
 };
 
-// unique keys, and the hi end of each as a word (hi << 32) for the hi-side degree sort
+// unique keys, and the hi end of each (32 bits) for the hi-side degree sort
 __global__ void k_compact_unique(const uint64_t* __restrict__ k, size_t n, int bits,
                                  const uint32_t* __restrict__ pos, uint64_t* __restrict__ out,
-                                 uint64_t* __restrict__ hi_words) {
+                                 uint32_t* __restrict__ hi_ends) {
     const uint64_t loop = (1ull << (2 * bits)) - 1, mask = (1ull << bits) - 1;
     GRID_STRIDE(i, n) {
         const uint64_t x = k[i];
         if (x != loop && (i == 0 || k[i - 1] != x)) {
             out[pos[i]] = x;
-            hi_words[pos[i]] = (x & mask) << 32;
+            hi_ends[pos[i]] = (uint32_t)(x & mask);
         }
     }
 }
@@ -84,6 +84,11 @@ struct GroupShift {
     const uint64_t* k;
     int shift;
     __device__ uint32_t operator()(size_t i) const { return (uint32_t)(k[i] >> shift); }
+};
+
+struct Group32 {
+    const uint32_t* k;
+    __device__ uint32_t operator()(size_t i) const { return k[i]; }
 };
 
 // deg[v] = (lo-side run length) + (hi-side run length)
@@ -130,12 +135,6 @@ struct I32In {
     const int32_t* p;
     int64_t n;
     __device__ OffT operator()(size_t i) const { return (int64_t)i < n ? (OffT)p[i] : OffT(0); }
-};
-
-struct LenIn {
-    const int32_t* p;
-    size_t n;
-    __device__ uint64_t operator()(size_t i) const { return i < n ? (uint64_t)(uint32_t)p[i] : 0ull; }
 };
 
 // ---- rows of the oriented CSR: after the sort by source rank, each row's entries are in
@@ -375,24 +374,34 @@ __global__ void k_count_kept(const uint64_t* __restrict__ words, size_t m, int b
     *out = (uint32_t)lo;
 }
 
-// in-edge k (sorted by v, then by edge index, so by u): its edge index is the word's low half
+// In-edge k (sorted by v, then by edge index, so by u): its edge index is the word's low half.
+// Also work[v] = sum of the tail lengths of v's in-edges (zeroed by the caller): lanes of a wave
+// hold consecutive k, so each run of equal v within the wave is summed by a scan and added with
+// one atomic by its last lane.
 template <typename OffT>
 __global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const EdgePay* __restrict__ pay,
-                          int32_t* __restrict__ in_u, OffT* __restrict__ in_start, int32_t* __restrict__ in_len) {
+                          int32_t* __restrict__ in_u, OffT* __restrict__ in_start, int32_t* __restrict__ in_len,
+                          unsigned long long* __restrict__ work) {
+    const int lane = lane_id();
     GRID_STRIDE(k, kept) {
-        const uint32_t i = (uint32_t)(words[k] & 0xffffffffull);
+        const uint64_t wd = words[k];
+        const uint32_t i = (uint32_t)(wd & 0xffffffffull);
+        const uint32_t v = (uint32_t)(wd >> 32);
         const EdgePay e = pay[i];
         in_u[k] = e.u;
         in_start[k] = (OffT)i + 1;
         in_len[k] = e.len;
+        // lanes past the end are inactive; lane l's run starts at the last head at or below l
+        const uint32_t vp = (uint32_t)__shfl_up((int)v, 1, kWave);
+        const uint32_t vn = (uint32_t)__shfl_down((int)v, 1, kWave);
+        const bool head = lane == 0 || vp != v;
+        const bool tail = lane == kWave - 1 || k + 1 == kept || vn != v;
+        const unsigned long long incl = wave_inclusive_scan((unsigned long long)(uint32_t)e.len);
+        const unsigned long long heads = __builtin_amdgcn_ballot_w64(head);
+        const int start = 63 - __builtin_clzll(heads & (~0ull >> (kWave - 1 - lane)));
+        const unsigned long long before = __shfl(incl, start > 0 ? start - 1 : 0, kWave);
+        if (tail) atomicAdd(&work[v], incl - (start > 0 ? before : 0ull));
     }
-}
-
-// work[v] = sum of the tail lengths of v's in-edges = prefix[in_off[v+1]] - prefix[in_off[v]]
-template <typename OffT>
-__global__ void k_work(const OffT* __restrict__ in_off, const uint64_t* __restrict__ prefix, int64_t n,
-                       uint64_t* __restrict__ work) {
-    GRID_STRIDE(v, n) work[v] = prefix[in_off[v + 1]] - prefix[in_off[v]];
 }
 
 // stats[0] = max |N+|, stats[1] = max degree, stats[2] = sum of work (wedges),
@@ -545,7 +554,6 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_TRY(tmp.get(rs_bytes + sizeof(uint64_t) * scan_scratch_elems(K + 1) + 1024, (uint8_t**)&sort_scratch));
     uint32_t* scan32 = (uint32_t*)((uint8_t*)sort_scratch + rs_bytes);
     OffT* scanO = (OffT*)scan32;
-    uint64_t* scan64 = (uint64_t*)scan32;
     int* bad;  // [0]: an endpoint outside [0, n); [1]: a sort's look-back wait gave up
     TCL_TRY(tmp.get(16, &bad));
     TCL_HIP(fill<int>(bad, 16, 0, st));
@@ -569,7 +577,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         TCL_HIP(radix_sort_u64(ka, kb, M, 0, 2 * bits, sort_scratch, sort_err, st, &sorted));
         ukeys = (sorted == ka) ? kb : ka;
         TCL_HIP(exclusive_scan<uint32_t>(UniqueFlag{sorted, M, (1ull << (2 * bits)) - 1}, M + 1, pos, scan32, st));
-        k_compact_unique<<<grid_for(M, kB, 8192), kB, 0, st>>>(sorted, M, bits, pos, ukeys, kc);
+        k_compact_unique<<<grid_for(M, kB, 8192), kB, 0, st>>>(sorted, M, bits, pos, ukeys, (uint32_t*)kc);
         TCL_HIP(hipGetLastError());
         int hb = 0;
         TCL_HIP(hipMemcpyAsync(&m32, pos + M, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -588,12 +596,12 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     }
     uint64_t* spare = (ukeys == ka) ? kb : ka;  // held the raw sorted keys, free from here on
     // degrees: lo ends are runs of the (lo, hi)-sorted unique keys; hi ends are runs after a
-    // stable sort of the words (hi << 32) on their high bits
+    // sort of the 32-bit hi ends
     TCL_HIP(run_bounds(GroupShift{ukeys, bits}, m, f1, l1, n, st));
     {
-        uint64_t* hs = kc;
-        if (m > 0) TCL_HIP(radix_sort_u64(kc, spare, m, 32, bits, sort_scratch, sort_err, st, &hs));
-        TCL_HIP(run_bounds(GroupShift{hs, 32}, m, f2, l2, n, st));
+        uint32_t* hs = (uint32_t*)kc;
+        if (m > 0) TCL_HIP(radix_sort_u32((uint32_t*)kc, (uint32_t*)spare, m, 0, bits, sort_scratch, sort_err, st, &hs));
+        TCL_HIP(run_bounds(Group32{hs}, m, f2, l2, n, st));
     }
     k_degrees<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, f2, l2, n, deg);
     TCL_HIP(hipGetLastError());
@@ -708,14 +716,12 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f2, l2, n, din);
     TCL_HIP(hipGetLastError());
     TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{din, n}, N + 1, in_off, scanO, st));
+    TCL_HIP(fill<uint64_t>(d.work, N, 0ull, st));
     if (kept > 0) {
-        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, pay, d.in_u, in_start, d.in_len);
+        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, pay, d.in_u, in_start, d.in_len,
+                                                                 (unsigned long long*)d.work);
         TCL_HIP(hipGetLastError());
     }
-    uint64_t* prefix = (ws == wa) ? wb : wa;  // kept + 1 prefix sums of the tail lengths
-    TCL_HIP(exclusive_scan<uint64_t>(LenIn{d.in_len, (size_t)kept}, (size_t)kept + 1, prefix, scan64, st));
-    k_work<OffT><<<grid_for(N, kB, 8192), kB, 0, st>>>(in_off, prefix, n, d.work);
-    TCL_HIP(hipGetLastError());
 
     mark(d, 4, st);
     // 5. run scratch and statistics

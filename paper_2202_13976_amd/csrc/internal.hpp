@@ -134,6 +134,8 @@ inline void mark(GraphDev& d, int i, hipStream_t st) {
 size_t radix_sort_scratch_bytes(size_t n);
 hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
                           unsigned int* err, hipStream_t st, uint64_t** result);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
+                          unsigned int* err, hipStream_t st, uint32_t** result);
 
 // build.hip
 tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,

@@ -1,4 +1,4 @@
-// LSD radix sort of 64-bit keys, 8-bit digits, one scatter kernel per digit pass.
+// LSD radix sort of 32- or 64-bit keys, 8-bit digits, one scatter kernel per digit pass.
 //
 // Before the passes, one kernel counts the digits of every pass in a single read of the
 // keys and a second turns those counts into the first output position of each digit,
@@ -37,13 +37,14 @@ __global__ void k_sort_zero(uint64_t* __restrict__ p, size_t n) {
 }
 
 // Digit counts of every pass: hist[p][d] for digit d of bits [lo_bit + 8p, lo_bit + 8p + 8).
-__global__ __launch_bounds__(256) void k_radix_count_all(const uint64_t* __restrict__ keys, size_t n, int lo_bit,
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_count_all(const K* __restrict__ keys, size_t n, int lo_bit,
                                                           int passes, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kMaxPasses * 256];
     for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const uint64_t key = keys[i] >> lo_bit;
+        const K key = keys[i] >> lo_bit;
         for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
     }
     __syncthreads();
@@ -68,8 +69,9 @@ __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_pass(const uint64_t* __restrict__ in,
-                                                             uint64_t* __restrict__ out, size_t n, int shift,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_pass(const K* __restrict__ in, K* __restrict__ out, size_t n,
+                                                             int shift,
                                                              const uint32_t* __restrict__ base,
                                                              uint64_t* __restrict__ status,
                                                              unsigned int* __restrict__ ticket,
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(const uint64_t* __r
     __shared__ uint32_t gstart[256];            // output position of the tile's first key of each digit
     __shared__ uint32_t scan_lds[256 / kWave];
     __shared__ unsigned int s_tile;
-    __shared__ uint64_t stage[kSortTile];
+    __shared__ K stage[kSortTile];
 
     const int lane = lane_id(), w = threadIdx.x / kWave;
     if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(const uint64_t* __r
     const size_t tile0 = tile * kSortTile;
     const size_t wbeg = tile0 + (size_t)w * kWaveSpan;
     const unsigned long long lt = lanemask_lt();
-    uint64_t k[kSortItems];
+    K k[kSortItems];
     uint32_t r[kSortItems];
     // every load is issued before any key is ranked (lanes past the end re-read the last key
     // and are left out of the peer masks)
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(const uint64_t* __r
     for (int c = 0; c < kSortItems; ++c) {
         const size_t idx = wbeg + (size_t)c * kWave + lane;
         const bool valid = idx < n;
-        const uint64_t key = k[c];
+        const K key = k[c];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         // peers: valid lanes whose digit equals this lane's, one bit of the digit at a time
         unsigned long long peers = __builtin_amdgcn_ballot_w64(valid);
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(const uint64_t* __r
     const size_t rem = n - tile0;
     const int tile_n = rem < (size_t)kSortTile ? (int)rem : kSortTile;
     for (int i = threadIdx.x; i < tile_n; i += kSortThreads) {
-        const uint64_t key = stage[i];
+        const K key = stage[i];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         out[(size_t)gstart[d] + (uint32_t)i - tstart[d]] = key;
     }
@@ -195,38 +197,49 @@ size_t radix_sort_scratch_bytes(size_t n) {
 // the range up to the next multiple of 8 take part, so callers keep them zero).
 // Ping-pongs between keys and alt; *result points at whichever holds the sorted keys.
 // err (device) is raised if a look-back wait gave up.
-hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
-                          unsigned int* err, hipStream_t st, uint64_t** result) {
+template <typename K>
+static hipError_t radix_sort(K* keys, K* alt, size_t n, int lo_bit, int nbits, void* scratch, unsigned int* err,
+                             hipStream_t st, K** result) {
     *result = keys;
     if (n <= 1 || nbits <= 0) return hipSuccess;
     if (n >= (1ull << 32)) return hipErrorInvalidValue;
     const int passes = (nbits + 7) / 8;
-    if (passes > kMaxPasses) return hipErrorInvalidValue;
+    if (passes > kMaxPasses || lo_bit + 8 * passes > (int)(8 * sizeof(K))) return hipErrorInvalidValue;
     const size_t tiles = sort_tiles(n);
     uint32_t* hist = (uint32_t*)scratch;
     uint32_t* bases = hist + kMaxPasses * 256;
     unsigned int* tickets = bases + kMaxPasses * 256;
     uint64_t* status = (uint64_t*)((uint8_t*)scratch + kHeadWords * sizeof(uint32_t));
     k_sort_zero<<<4, 256, 0, st>>>((uint64_t*)scratch, kHeadWords / 2);
-    k_radix_count_all<<<(unsigned)std::min<size_t>((n + 4095) / 4096, 2048), 256, 0, st>>>(keys, n, lo_bit, passes,
-                                                                                          hist);
+    k_radix_count_all<K><<<(unsigned)std::min<size_t>((n + 4095) / 4096, 2048), 256, 0, st>>>(keys, n, lo_bit,
+                                                                                             passes, hist);
     k_radix_bases<<<1, 256, 0, st>>>(hist, passes, bases);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    uint64_t* a = keys;
-    uint64_t* b = alt;
+    K* a = keys;
+    K* b = alt;
     for (int p = 0; p < passes; ++p) {
         k_sort_zero<<<(unsigned)std::min<size_t>((tiles * 256 + 255) / 256, 4096), 256, 0, st>>>(status, tiles * 256);
-        k_radix_pass<<<(unsigned)tiles, kSortThreads, 0, st>>>(a, b, n, lo_bit + 8 * p, bases + p * 256, status,
-                                                               tickets + p, err);
+        k_radix_pass<K><<<(unsigned)tiles, kSortThreads, 0, st>>>(a, b, n, lo_bit + 8 * p, bases + p * 256, status,
+                                                                  tickets + p, err);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        uint64_t* t = a;
+        K* t = a;
         a = b;
         b = t;
     }
     *result = a;
     return hipSuccess;
+}
+
+hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
+                          unsigned int* err, hipStream_t st, uint64_t** result) {
+    return radix_sort<uint64_t>(keys, alt, n, lo_bit, nbits, scratch, err, st, result);
+}
+
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
+                          unsigned int* err, hipStream_t st, uint32_t** result) {
+    return radix_sort<uint32_t>(keys, alt, n, lo_bit, nbits, scratch, err, st, result);
 }
 
 }  // namespace tcl

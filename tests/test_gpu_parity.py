@@ -259,4 +259,7 @@ def test_builder_structure(ctx, row_sort_max):
     # kept in-edges: oriented edges with a nonempty tail whose target has a nonempty N+
     dplus = np.diff(off)
     tail = off[src + 1] - np.arange(len(adj)) - 1
-    assert info.kept_in_edges == int(np.count_nonzero((tail > 0) & (dplus[adj] > 0)))
+    kept = (tail > 0) & (dplus[adj] > 0)
+    assert info.kept_in_edges == int(np.count_nonzero(kept))
+    # probes (oriented wedges that can close): the sum of the kept in-edges' tail lengths
+    assert info.wedges == int(tail[kept].sum())
