@@ -55,16 +55,45 @@ struct UniqueFlag {
     }
 };
 
-// unique keys, and the hi end of each (32 bits) for the hi-side degree sort
-__global__ void k_compact_unique(const uint64_t* __restrict__ k, size_t n, int bits,
-                                 const uint32_t* __restrict__ pos, uint64_t* __restrict__ out,
-                                 uint32_t* __restrict__ hi_ends) {
+// Unique keys of one tile of kScanTile sorted keys, written at the tile's offset (the
+// exclusive sum of the earlier tiles' unique counts), with the hi end of each (32 bits) for the
+// hi-side degree sort.  Element i * 256 + t of the tile is thread t's i-th: one ballot per wave
+// and round gives the ranks, one scan over the 16 x 4 (round, wave) counts the bases.
+__global__ __launch_bounds__(kScanThreads) void k_unique_tiles(const uint64_t* __restrict__ k, size_t n, int bits,
+                                                               const uint32_t* __restrict__ tile_off,
+                                                               uint64_t* __restrict__ out,
+                                                               uint32_t* __restrict__ hi_ends) {
+    constexpr int NW = kScanThreads / kWave;
+    static_assert(kScanItems * NW == kWave, "one lane per (round, wave) count");
+    __shared__ uint32_t base[kScanItems][NW];
     const uint64_t loop = (1ull << (2 * bits)) - 1, mask = (1ull << bits) - 1;
-    GRID_STRIDE(i, n) {
-        const uint64_t x = k[i];
-        if (x != loop && (i == 0 || k[i - 1] != x)) {
-            out[pos[i]] = x;
-            hi_ends[pos[i]] = (uint32_t)(x & mask);
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const unsigned long long lt = lanemask_lt();
+    const size_t tile = (size_t)blockIdx.x * kScanTile;
+    uint64_t x[kScanItems];
+    unsigned long long bal[kScanItems];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const size_t e = tile + (size_t)i * kScanThreads + threadIdx.x;
+        x[i] = e < n ? k[e] : loop;
+        uint64_t prev = __shfl_up(x[i], 1, kWave);
+        if (lane == 0) prev = (e > 0 && e < n) ? k[e - 1] : ~x[i];
+        bal[i] = __builtin_amdgcn_ballot_w64(x[i] != loop && (e == 0 || prev != x[i]));
+        if (lane == 0) base[i][w] = (uint32_t)__popcll(bal[i]);
+    }
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t c = base[lane / NW][lane % NW];
+        base[lane / NW][lane % NW] = wave_inclusive_scan(c) - c;
+    }
+    __syncthreads();
+    const uint32_t t0 = tile_off[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if ((bal[i] >> lane) & 1ull) {
+            const uint32_t p = t0 + base[i][w] + (uint32_t)__popcll(bal[i] & lt);
+            out[p] = x[i];
+            hi_ends[p] = (uint32_t)(x[i] & mask);
         }
     }
 }
@@ -576,11 +605,18 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         TCL_HIP(hipGetLastError());
         TCL_HIP(radix_sort_u64(ka, kb, M, 0, 2 * bits, sort_scratch, sort_err, st, &sorted));
         ukeys = (sorted == ka) ? kb : ka;
-        TCL_HIP(exclusive_scan<uint32_t>(UniqueFlag{sorted, M, (1ull << (2 * bits)) - 1}, M + 1, pos, scan32, st));
-        k_compact_unique<<<grid_for(M, kB, 8192), kB, 0, st>>>(sorted, M, bits, pos, ukeys, (uint32_t*)kc);
+        // unique counts per tile, their exclusive sums (tiles + 1 entries: the last is m), then
+        // the unique keys written straight to their positions
+        const size_t tiles = (M + kScanTile - 1) / kScanTile;
+        uint32_t* toff = pos;
+        k_reduce_tiles<uint32_t, UniqueFlag><<<(unsigned)tiles, kScanThreads, 0, st>>>(
+            UniqueFlag{sorted, M, (1ull << (2 * bits)) - 1}, M, toff);
+        TCL_HIP(hipGetLastError());
+        TCL_HIP(exclusive_scan<uint32_t>(ArrayIn<uint32_t>{toff, tiles}, tiles + 1, toff, scan32, st));
+        k_unique_tiles<<<(unsigned)tiles, kScanThreads, 0, st>>>(sorted, M, bits, toff, ukeys, (uint32_t*)kc);
         TCL_HIP(hipGetLastError());
         int hb = 0;
-        TCL_HIP(hipMemcpyAsync(&m32, pos + M, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipMemcpyAsync(&m32, toff + tiles, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipStreamSynchronize(st));
         if (hb) {
