@@ -37,19 +37,42 @@ __global__ void k_sort_zero(uint64_t* __restrict__ p, size_t n) {
 }
 
 // Digit counts of every pass: hist[p][d] for digit d of bits [lo_bit + 8p, lo_bit + 8p + 8).
+// Each block keeps kCountCopies copies of its counters, lane l adding to copy l % kCountCopies,
+// so lanes with equal digits (common in the high digits of skewed keys) contend on fewer
+// addresses; the copies of one counter are adjacent words, in different banks.
+constexpr int kCountCopies = 4;
+constexpr int kCountItems = 4;  // keys per thread and round, loaded before any is counted
+
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_count_all(const K* __restrict__ keys, size_t n, int lo_bit,
                                                           int passes, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kMaxPasses * 256];
-    for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) h[i] = 0;
+    __shared__ uint32_t h[kMaxPasses * 256 * kCountCopies];
+    for (int i = threadIdx.x; i < passes * 256 * kCountCopies; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const K key = keys[i] >> lo_bit;
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+    const uint32_t copy = (uint32_t)lane_id() % kCountCopies;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i0 < n; i0 += stride * kCountItems) {
+        K kk[kCountItems];
+#pragma unroll
+        for (int q = 0; q < kCountItems; ++q) {
+            const size_t i = i0 + (size_t)q * stride;
+            kk[q] = i < n ? keys[i] : K(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kCountItems; ++q) {
+            if (i0 + (size_t)q * stride >= n) break;
+            const K key = kk[q] >> lo_bit;
+            for (int p = 0; p < passes; ++p)
+                atomicAdd(&h[((p * 256 + (uint32_t)((key >> (8 * p)) & 255u)) * kCountCopies) + copy], 1u);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < passes * 256; i += blockDim.x)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+    for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < kCountCopies; ++r) c += h[i * kCountCopies + r];
+        if (c) atomicAdd(&hist[i], c);
+    }
 }
 
 // First output position of each digit, per pass (one block of 256 threads).
@@ -211,8 +234,8 @@ static hipError_t radix_sort(K* keys, K* alt, size_t n, int lo_bit, int nbits, v
     unsigned int* tickets = bases + kMaxPasses * 256;
     uint64_t* status = (uint64_t*)((uint8_t*)scratch + kHeadWords * sizeof(uint32_t));
     k_sort_zero<<<4, 256, 0, st>>>((uint64_t*)scratch, kHeadWords / 2);
-    k_radix_count_all<K><<<(unsigned)std::min<size_t>((n + 4095) / 4096, 2048), 256, 0, st>>>(keys, n, lo_bit,
-                                                                                             passes, hist);
+    k_radix_count_all<K><<<(unsigned)std::min<size_t>((n + 16383) / 16384, 1024), 256, 0, st>>>(keys, n, lo_bit,
+                                                                                               passes, hist);
     k_radix_bases<<<1, 256, 0, st>>>(hist, passes, bases);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
