@@ -18,6 +18,7 @@
 // |N+(r)| <= sqrt(2m), and relabelling by rank keeps every list sorted by rank: the
 // entries of N+(u) after v are exactly the candidates w > v that close a triangle
 // (u, v, w), the rank-space form of the upper-triangle offset of Sec. II-C.
+#include "digits.hpp"
 #include "internal.hpp"
 #include "scan.hpp"
 
@@ -28,6 +29,9 @@ constexpr int kB = 256;
 #define GRID_STRIDE(i, n) \
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)(n); i += (size_t)gridDim.x * blockDim.x)
 
+// Canonical keys (lo << bits | hi); a self-loop gets the all-ones key, dropped after the sort.
+// (Their digits are counted by the sort itself: six LDS counts per key cost more here than
+// the extra read there.)
 __global__ void k_make_keys(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, size_t m_in,
                             int64_t n, int bits, uint64_t* __restrict__ keys, int* __restrict__ bad) {
     const uint64_t loop = (1ull << (2 * bits)) - 1;
@@ -143,15 +147,24 @@ __global__ void k_rank_scatter(const uint64_t* __restrict__ rk, int64_t n, int b
     }
 }
 
-__global__ void k_relabel(const uint64_t* __restrict__ uk, size_t m, int bits, const int32_t* __restrict__ rank,
-                          uint64_t* __restrict__ ok) {
+// Oriented keys in rank space (lower rank << bits | higher rank), with the digits of the
+// source rank counted for the sort by source that follows.
+__global__ __launch_bounds__(kB) void k_relabel(const uint64_t* __restrict__ uk, size_t m, int bits,
+                                                const int32_t* __restrict__ rank, uint64_t* __restrict__ ok,
+                                                uint32_t* __restrict__ hist) {
+    __shared__ DigitCounts dc;
+    const int passes = digit_passes(bits);
+    dc.clear(passes);
     const uint64_t mask = (1ull << bits) - 1;
     GRID_STRIDE(i, m) {
         const uint64_t x = uk[i];
         const uint32_t ra = (uint32_t)rank[x >> bits], rb = (uint32_t)rank[x & mask];
         const uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
-        ok[i] = ((uint64_t)lo << bits) | hi;
+        const uint64_t key = ((uint64_t)lo << bits) | hi;
+        ok[i] = key;
+        dc.add(key, bits, passes);
     }
+    dc.flush(hist, passes);
 }
 
 __global__ void k_run_counts(const uint32_t* __restrict__ f, const uint32_t* __restrict__ l, int64_t n,
@@ -376,9 +389,13 @@ struct EdgePay {
 // An edge that cannot close a triangle (empty tail, or N+(v) empty) gets the key 2^bits,
 // above every vertex, so it sorts after all in-edges that are kept.
 template <typename OffT>
-__global__ void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits, const OffT* __restrict__ out_off,
-                            const int32_t* __restrict__ dplus, int32_t* __restrict__ adj,
-                            uint64_t* __restrict__ words, EdgePay* __restrict__ pay) {
+__global__ __launch_bounds__(kB) void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits,
+                                                  const OffT* __restrict__ out_off, const int32_t* __restrict__ dplus,
+                                                  int32_t* __restrict__ adj, uint64_t* __restrict__ words,
+                                                  EdgePay* __restrict__ pay, uint32_t* __restrict__ hist) {
+    __shared__ DigitCounts dc;
+    const int passes = digit_passes(bits + 1);
+    dc.clear(passes);
     const uint64_t mask = (1ull << bits) - 1;
     GRID_STRIDE(i, m) {
         const uint64_t x = ok[i];
@@ -386,9 +403,12 @@ __global__ void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits,
         adj[i] = (int32_t)v;
         const int64_t len = (int64_t)out_off[u + 1] - (int64_t)i - 1;
         const bool kept = len > 0 && dplus[v] > 0;
-        words[i] = ((kept ? (uint64_t)v : (1ull << bits)) << 32) | (uint64_t)i;
+        const uint64_t w = ((kept ? (uint64_t)v : (1ull << bits)) << 32) | (uint64_t)i;
+        words[i] = w;
         pay[i] = EdgePay{(int32_t)u, (int32_t)len};
+        dc.add(w, 32, passes);
     }
+    dc.flush(hist, passes);
 }
 
 // Number of leading words whose key is below 2^bits (the kept in-edges), by bisection.
@@ -652,7 +672,9 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         uint64_t* rs = spare;
         k_rank_keys<<<grid_for(N, kB, 8192), kB, 0, st>>>(deg, n, bits, spare);
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(spare, kc, N, 0, 2 * bits, sort_scratch, sort_err, st, &rs));
+        // the keys are written in vertex order, so a stable sort on the degree bits alone
+        // (degrees are below n <= 2^bits) orders them by (degree, id)
+        TCL_HIP(radix_sort_u64(spare, kc, N, bits, bits, sort_scratch, sort_err, st, &rs));
         k_rank_scatter<<<grid_for(N, kB, 8192), kB, 0, st>>>(rs, n, bits, d.order, rank, d.deg_r);
         TCL_HIP(hipGetLastError());
     }
@@ -667,9 +689,10 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     d.out_off = out_off;
     TCL_TRY(keep(g, std::max<size_t>(m, 1), &d.adj));
     if (m > 0) {
-        k_relabel<<<grid_for(m, kB, 8192), kB, 0, st>>>(ukeys, m, bits, rank, okeys);
+        TCL_HIP(radix_counts_clear(sort_scratch, st));
+        k_relabel<<<grid_for(m, kB, 1024), kB, 0, st>>>(ukeys, m, bits, rank, okeys, radix_counts(sort_scratch));
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(okeys, kc, m, bits, bits, sort_scratch, sort_err, st, &osorted));
+        TCL_HIP(radix_sort_u64(okeys, kc, m, bits, bits, sort_scratch, sort_err, st, &osorted, true));
     }
     TCL_HIP(run_bounds(GroupShift{osorted, bits}, m, f1, l1, n, st));
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, n, d.dplus);
@@ -727,9 +750,11 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     uint64_t* ws = wa;
     TCL_TRY(tmp.get(std::max<size_t>(m, 1), &pay));
     if (m > 0) {
-        k_edge_emit<OffT><<<grid_for(m, kB, 8192), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, d.adj, wa, pay);
+        TCL_HIP(radix_counts_clear(sort_scratch, st));
+        k_edge_emit<OffT><<<grid_for(m, kB, 1024), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, d.adj, wa, pay,
+                                                                radix_counts(sort_scratch));
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(wa, wb, m, 32, bits + 1, sort_scratch, sort_err, st, &ws));
+        TCL_HIP(radix_sort_u64(wa, wb, m, 32, bits + 1, sort_scratch, sort_err, st, &ws, true));
         uint32_t* kc_dev = (uint32_t*)(bad + 5);
         k_count_kept<<<1, 1, 0, st>>>(ws, m, bits, kc_dev);
         TCL_HIP(hipGetLastError());
@@ -878,7 +903,9 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     k_classify<<<grid_for(n, kB, 4096), kB, 0, st>>>((const unsigned long long*)d.work, d.dplus, d.n, d.bits,
                                                      tn.wave_work_max, wave_cap, block_cap, group, ka, counts);
     TCL_HIP(hipGetLastError());
-    TCL_HIP(radix_sort_u64(ka, kb, n, 0, d.bits + 6, scr, sort_err, st, &res));
+    // keys are written in vertex order: a stable sort on the 6 class bits keeps vertices
+    // ascending within a class
+    TCL_HIP(radix_sort_u64(ka, kb, n, d.bits, 6, scr, sort_err, st, &res));
     unsigned long long hc[64];
     unsigned int herr = 0;
     TCL_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st));

@@ -133,9 +133,13 @@ inline void mark(GraphDev& d, int i, hipStream_t st) {
 // radix.hip
 size_t radix_sort_scratch_bytes(size_t n);
 hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
-                          unsigned int* err, hipStream_t st, uint64_t** result);
+                          unsigned int* err, hipStream_t st, uint64_t** result, bool counted = false);
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
-                          unsigned int* err, hipStream_t st, uint32_t** result);
+                          unsigned int* err, hipStream_t st, uint32_t** result, bool counted = false);
+// counted = true: the caller has cleared the digit counts of the scratch (radix_counts_clear)
+// and a kernel writing the keys has added every key's digits to radix_counts(scratch)
+uint32_t* radix_counts(void* scratch);
+hipError_t radix_counts_clear(void* scratch, hipStream_t st);
 
 // build.hip
 tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,

@@ -15,6 +15,7 @@
 //     wait ends; as a guard, a wait longer than a fixed number of polls raises the
 //     error flag and gives up (the result is then wrong and the caller reports it);
 //   * the tile is staged in LDS in digit order and written out in runs.
+#include "digits.hpp"
 #include "internal.hpp"
 #include "scan.hpp"
 
@@ -25,7 +26,6 @@ constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortItems = 32;                        // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;  // 16384 keys per tile (128 KiB staged in LDS)
 constexpr int kWaveSpan = kSortTile / kSortWaves;     // 2048 keys per wave
-constexpr int kMaxPasses = 8;
 constexpr uint64_t kAggregate = 1ull << 62;  // status: the tile's own count is published
 constexpr uint64_t kInclusive = 2ull << 62;  // status: the running total through the tile
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
@@ -37,19 +37,13 @@ __global__ void k_sort_zero(uint64_t* __restrict__ p, size_t n) {
 }
 
 // Digit counts of every pass: hist[p][d] for digit d of bits [lo_bit + 8p, lo_bit + 8p + 8).
-// Each block keeps kCountCopies copies of its counters, lane l adding to copy l % kCountCopies,
-// so lanes with equal digits (common in the high digits of skewed keys) contend on fewer
-// addresses; the copies of one counter are adjacent words, in different banks.
-constexpr int kCountCopies = 4;
 constexpr int kCountItems = 4;  // keys per thread and round, loaded before any is counted
 
 template <typename K>
 __global__ __launch_bounds__(256) void k_radix_count_all(const K* __restrict__ keys, size_t n, int lo_bit,
                                                           int passes, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kMaxPasses * 256 * kCountCopies];
-    for (int i = threadIdx.x; i < passes * 256 * kCountCopies; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const uint32_t copy = (uint32_t)lane_id() % kCountCopies;
+    __shared__ DigitCounts dc;
+    dc.clear(passes);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i0 < n; i0 += stride * kCountItems) {
         K kk[kCountItems];
@@ -61,18 +55,10 @@ __global__ __launch_bounds__(256) void k_radix_count_all(const K* __restrict__ k
 #pragma unroll
         for (int q = 0; q < kCountItems; ++q) {
             if (i0 + (size_t)q * stride >= n) break;
-            const K key = kk[q] >> lo_bit;
-            for (int p = 0; p < passes; ++p)
-                atomicAdd(&h[((p * 256 + (uint32_t)((key >> (8 * p)) & 255u)) * kCountCopies) + copy], 1u);
+            dc.add(kk[q], lo_bit, passes);
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int r = 0; r < kCountCopies; ++r) c += h[i * kCountCopies + r];
-        if (c) atomicAdd(&hist[i], c);
-    }
+    dc.flush(hist, passes);
 }
 
 // First output position of each digit, per pass (one block of 256 threads).
@@ -222,7 +208,7 @@ size_t radix_sort_scratch_bytes(size_t n) {
 // err (device) is raised if a look-back wait gave up.
 template <typename K>
 static hipError_t radix_sort(K* keys, K* alt, size_t n, int lo_bit, int nbits, void* scratch, unsigned int* err,
-                             hipStream_t st, K** result) {
+                             hipStream_t st, K** result, bool counted) {
     *result = keys;
     if (n <= 1 || nbits <= 0) return hipSuccess;
     if (n >= (1ull << 32)) return hipErrorInvalidValue;
@@ -233,9 +219,14 @@ static hipError_t radix_sort(K* keys, K* alt, size_t n, int lo_bit, int nbits, v
     uint32_t* bases = hist + kMaxPasses * 256;
     unsigned int* tickets = bases + kMaxPasses * 256;
     uint64_t* status = (uint64_t*)((uint8_t*)scratch + kHeadWords * sizeof(uint32_t));
-    k_sort_zero<<<4, 256, 0, st>>>((uint64_t*)scratch, kHeadWords / 2);
-    k_radix_count_all<K><<<(unsigned)std::min<size_t>((n + 16383) / 16384, 1024), 256, 0, st>>>(keys, n, lo_bit,
+    if (counted) {
+        // the digit counts are already in place: clear bases and tickets only
+        k_sort_zero<<<4, 256, 0, st>>>((uint64_t*)(hist + kMaxPasses * 256), (kHeadWords - kMaxPasses * 256) / 2);
+    } else {
+        k_sort_zero<<<4, 256, 0, st>>>((uint64_t*)scratch, kHeadWords / 2);
+        k_radix_count_all<K><<<(unsigned)std::min<size_t>((n + 16383) / 16384, 1024), 256, 0, st>>>(keys, n, lo_bit,
                                                                                                passes, hist);
+    }
     k_radix_bases<<<1, 256, 0, st>>>(hist, passes, bases);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -256,13 +247,20 @@ static hipError_t radix_sort(K* keys, K* alt, size_t n, int lo_bit, int nbits, v
 }
 
 hipError_t radix_sort_u64(uint64_t* keys, uint64_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
-                          unsigned int* err, hipStream_t st, uint64_t** result) {
-    return radix_sort<uint64_t>(keys, alt, n, lo_bit, nbits, scratch, err, st, result);
+                          unsigned int* err, hipStream_t st, uint64_t** result, bool counted) {
+    return radix_sort<uint64_t>(keys, alt, n, lo_bit, nbits, scratch, err, st, result, counted);
 }
 
 hipError_t radix_sort_u32(uint32_t* keys, uint32_t* alt, size_t n, int lo_bit, int nbits, void* scratch,
-                          unsigned int* err, hipStream_t st, uint32_t** result) {
-    return radix_sort<uint32_t>(keys, alt, n, lo_bit, nbits, scratch, err, st, result);
+                          unsigned int* err, hipStream_t st, uint32_t** result, bool counted) {
+    return radix_sort<uint32_t>(keys, alt, n, lo_bit, nbits, scratch, err, st, result, counted);
+}
+
+uint32_t* radix_counts(void* scratch) { return (uint32_t*)scratch; }
+
+hipError_t radix_counts_clear(void* scratch, hipStream_t st) {
+    k_sort_zero<<<4, 256, 0, st>>>((uint64_t*)scratch, kMaxPasses * 256 / 2);
+    return hipGetLastError();
 }
 
 }  // namespace tcl
