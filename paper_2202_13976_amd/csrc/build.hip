@@ -358,16 +358,17 @@ __global__ __launch_bounds__(256) void k_row_sort_long(uint64_t* __restrict__ ke
     }
 }
 
-// rows of more than 64 entries (flag for the scan that lists them)
+// rows of more than lim entries (flag for the scan that lists them)
 struct LongRow {
     const int32_t* dplus;
     int64_t n;
-    __device__ uint32_t operator()(size_t i) const { return ((int64_t)i < n && dplus[i] > kWave) ? 1u : 0u; }
+    int32_t lim;
+    __device__ uint32_t operator()(size_t i) const { return ((int64_t)i < n && dplus[i] > lim) ? 1u : 0u; }
 };
 
-__global__ void k_list_rows(const int32_t* __restrict__ dplus, int64_t n, const uint32_t* __restrict__ pos,
-                            int32_t* __restrict__ rows) {
-    GRID_STRIDE(r, n) if (dplus[r] > kWave) rows[pos[r]] = (int32_t)r;
+__global__ void k_list_rows(const int32_t* __restrict__ dplus, int64_t n, int32_t lim,
+                            const uint32_t* __restrict__ pos, int32_t* __restrict__ rows) {
+    GRID_STRIDE(r, n) if (dplus[r] > lim) rows[pos[r]] = (int32_t)r;
 }
 
 __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int* __restrict__ out) {
@@ -702,14 +703,18 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         int* mx = bad + 4;
         k_max_i32<<<grid_for(N, kB, 1024), kB, 0, st>>>(d.dplus, n, mx);
         TCL_HIP(hipGetLastError());
-        // the rows longer than a wave, listed (rpos: scan of their flags)
-        uint32_t* rpos;
+        // the rows longer than a wave and those longer than 1024, listed (scans of their flags)
+        constexpr int32_t kMid = 1024;
+        uint32_t *rpos, *rpos2;
         TCL_TRY(tmp.get(N + 1, &rpos));
-        TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n}, N + 1, rpos, scan32, st));
+        TCL_TRY(tmp.get(N + 1, &rpos2));
+        TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n, kWave}, N + 1, rpos, scan32, st));
+        TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n, kMid}, N + 1, rpos2, scan32, st));
         int dmax = 0;
-        uint32_t nlong = 0;
+        uint32_t nlong = 0, nlong2 = 0;
         TCL_HIP(hipMemcpyAsync(&dmax, mx, sizeof(int), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipMemcpyAsync(&nlong, rpos + N, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipMemcpyAsync(&nlong2, rpos2 + N, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipStreamSynchronize(st));
         if (dmax <= row_max) {
             const size_t groups = (N + kWave - 1) / kWave;
@@ -718,16 +723,20 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
             if (nlong > 0) {
                 int32_t* rows;
                 TCL_TRY(tmp.get(nlong, &rows));
-                k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, rpos, rows);
+                k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, kWave, rpos, rows);
                 TCL_HIP(hipGetLastError());
-                k_row_sort_long<OffT, kWave, 1024><<<grid_for((size_t)nlong * kWave, kB, 8192), kB, 0, st>>>(
+                k_row_sort_long<OffT, kWave, kMid><<<grid_for((size_t)nlong * kWave, kB, 8192), kB, 0, st>>>(
                     osorted, out_off, rows, (int64_t)nlong, bits);
                 TCL_HIP(hipGetLastError());
-                if (dmax > 1024) {
-                    k_row_sort_long<OffT, 1024, kRowSortMax><<<grid_for((size_t)nlong * kWave, kB, 1024), kB, 0, st>>>(
-                        osorted, out_off, rows, (int64_t)nlong, bits);
-                    TCL_HIP(hipGetLastError());
-                }
+            }
+            if (nlong2 > 0) {
+                int32_t* rows2;
+                TCL_TRY(tmp.get(nlong2, &rows2));
+                k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, kMid, rpos2, rows2);
+                TCL_HIP(hipGetLastError());
+                k_row_sort_long<OffT, kMid, kRowSortMax><<<grid_for((size_t)nlong2 * kWave, kB, 4096), kB, 0, st>>>(
+                    osorted, out_off, rows2, (int64_t)nlong2, bits);
+                TCL_HIP(hipGetLastError());
             }
         } else {
             // a row too long for the LDS sort: sort the keys by (source, target) in full instead
