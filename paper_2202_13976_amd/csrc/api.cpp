@@ -303,9 +303,9 @@ extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* o
     out->wedges = g->d.wedges;
     out->device_bytes = g->d.device_bytes;
     out->kept_in_edges = g->d.m_in_kept;
-    out->active_vertices = g->d.n_block + g->d.n_wave + g->d.n_global;
+    out->active_vertices = g->d.n_block + g->d.n_wave + g->d.n_list + g->d.n_global;
     out->staged_entries = (int64_t)g->d.staged;
-    out->block_vertices = g->d.n_block;
+    out->block_vertices = g->d.n_block + g->d.n_list;
     out->count_grid = g->d.count_grid;
     out->count_lds_bytes = g->d.count_lds;
     out->count_blocks_per_cu = g->d.count_per_cu;

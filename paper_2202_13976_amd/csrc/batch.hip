@@ -477,7 +477,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     for (int i = 0; i < count; ++i) {
         const GraphDev& d = graphs[i]->d;
         const uint32_t r = region_need(d);
-        if (d.n_global > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
+        if (d.n_global > 0 || d.n_list > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
             solo.push_back(i);
             continue;
         }

@@ -839,11 +839,12 @@ tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
 
 // ------------------------------------------------------------------ schedule (degree/work bins)
 
-constexpr int kClassWave = 48, kClassGlobal = 50, kClassNone = 63;
+constexpr int kClassWave = 48, kClassList = 49, kClassGlobal = 50, kClassNone = 63;
 
 __global__ void k_classify(const unsigned long long* __restrict__ work, const int32_t* __restrict__ dplus,
                            int64_t n, int bits, int64_t wave_work_max, int32_t wave_cap, int32_t block_cap,
-                           int group, uint64_t* __restrict__ keys, unsigned long long* __restrict__ counts) {
+                           int32_t list_cap, int group, uint64_t* __restrict__ keys,
+                           unsigned long long* __restrict__ counts) {
     __shared__ unsigned int c[64];
     for (int i = threadIdx.x; i < 64; i += blockDim.x) c[i] = 0;
     __syncthreads();
@@ -853,8 +854,10 @@ __global__ void k_classify(const unsigned long long* __restrict__ work, const in
         int cls;
         if (w == 0) {
             cls = kClassNone;
-        } else if (dp > block_cap) {
+        } else if (dp > list_cap) {
             cls = kClassGlobal;
+        } else if (dp > block_cap) {
+            cls = kClassList;
         } else if (dp <= wave_cap && (group == 1 || (group == 0 && (int64_t)w <= wave_work_max))) {
             cls = kClassWave;
         } else {
@@ -893,6 +896,9 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     d.hash_slots = table_slots(probe, d.max_dplus);
     const bool sorted = probe == TC_LCC_PROBE_SORTED || probe == TC_LCC_PROBE_MERGE;
     const int32_t block_cap = sorted ? d.hash_slots : hash_capacity(d.hash_slots);
+    // beyond the hash, a block's table still holds a sorted list of as many entries as it has
+    // slots (not with the hash-only probe): such vertices get a launch of their own
+    const int32_t list_cap = probe == TC_LCC_PROBE_HASH ? block_cap : d.hash_slots;
     int32_t wave_cap = sorted ? d.hash_slots / kWavesPerBlock : hash_capacity(d.hash_slots / kWavesPerBlock);
     if (tn.wave_outdeg_max > 0 && tn.wave_outdeg_max < wave_cap) wave_cap = tn.wave_outdeg_max;
     Temps tmp{g->ctx->pool.get(), {}};
@@ -910,7 +916,8 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     TCL_HIP(fill<unsigned int>(sort_err, 64, 0u, st));
     const int group = tn.group;
     k_classify<<<grid_for(n, kB, 4096), kB, 0, st>>>((const unsigned long long*)d.work, d.dplus, d.n, d.bits,
-                                                     tn.wave_work_max, wave_cap, block_cap, group, ka, counts);
+                                                     tn.wave_work_max, wave_cap, block_cap, list_cap, group, ka,
+                                                     counts);
     TCL_HIP(hipGetLastError());
     // keys are written in vertex order: a stable sort on the 6 class bits keeps vertices
     // ascending within a class
@@ -931,8 +938,9 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     }
     d.n_block = nb;
     d.n_wave = (int64_t)hc[kClassWave];
+    d.n_list = (int64_t)hc[kClassList];
     d.n_global = (int64_t)hc[kClassGlobal];
-    const int64_t active = nb + d.n_wave + d.n_global;
+    const int64_t active = nb + d.n_wave + d.n_list + d.n_global;
     if (active > 0) {
         k_vlist<<<grid_for(active, kB, 4096), kB, 0, st>>>(res, active, d.bits, d.vlist);
         TCL_HIP(hipGetLastError());

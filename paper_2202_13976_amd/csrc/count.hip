@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
 
 // Vertices whose N+(v) exceeds the LDS table: binary search straight in N+(v) in
 // global memory, one wave per in-edge chunk of 64, per-entry counts go to t(w)
-// directly.  Only taken when |N+(v)| exceeds the largest table: 2048 keys (hash of 4096
-// slots at load 1/2) or 4096 (sorted list).
+// directly.  Only taken when |N+(v)| exceeds the largest table: 4096 keys (the table as a
+// sorted list), or 2048 with the hash-only probe (4096 slots at load 1/2).
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -183,9 +183,24 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, int merge_x100, int spare_per_
         d.count_lds = (int32_t)lds;
         d.count_per_cu = per_cu;
     }
+    if (d.n_list > 0) {
+        // block vertices whose lists exceed the hash: the block's table as a sorted list, one
+        // block each, with queue counters of their own (vlist: blocks, waves, these, global)
+        CountArgs<OffT> al = a;
+        al.vlist = d.vlist + d.n_block + d.n_wave;
+        al.n_block = d.n_list;
+        al.n_wave = 0;
+        al.ctr = d.counters + 2;
+        const size_t lds = (size_t)d.hash_slots * 8;
+        const unsigned grid = (unsigned)std::min<int64_t>(d.n_list, (int64_t)g->ctx->cu_count * 4);
+        k_count<OffT, TC_LCC_PROBE_SORTED><<<grid, kCountThreads, lds, st>>>(al);
+        TCL_HIP(hipGetLastError());
+    }
     if (d.n_global > 0) {
+        CountArgs<OffT> ag = a;
+        ag.vlist = d.vlist + d.n_list;  // k_count_global reads past the block and wave vertices
         const unsigned grid = (unsigned)std::min<int64_t>(d.n_global, (int64_t)g->ctx->cu_count * 4);
-        k_count_global<OffT><<<grid, 256, 0, st>>>(a);
+        k_count_global<OffT><<<grid, 256, 0, st>>>(ag);
         TCL_HIP(hipGetLastError());
     }
     return TC_LCC_OK;

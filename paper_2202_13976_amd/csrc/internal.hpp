@@ -82,6 +82,7 @@ struct GraphDev {
     unsigned int* counters = nullptr;      // [8] work-queue counters of the count kernel
     int32_t* vlist = nullptr;   // [n] scheduled vertices: block bin, wave bin, global bin
     int64_t n_block = 0, n_wave = 0, n_global = 0;
+    int64_t n_list = 0;         // block vertices too long for the hash: the table as a sorted list
     int64_t class_count[48] = {};  // block-class vertices per work class (class c: bit length 40 - c)
 
     int32_t hash_slots = 64;    // LDS hash slots of one block (power of two)

@@ -58,26 +58,34 @@ def test_batch_matches_oracle(ctx):
         g.free()
 
 
-def test_batch_mixed_widths_and_global_path(ctx):
-    """4- and 8-byte offsets in one batch, plus K_2800, whose out-lists exceed the largest LDS
-    table (checked against the closed form for K_n, which pins the oracle too)."""
-    print("[gpu] batch mixed widths + K2800", flush=True)
+@pytest.mark.parametrize("probe", ["auto", "hash"])
+def test_batch_mixed_widths_and_global_path(ctx, probe):
+    """4- and 8-byte offsets in one batch, plus K_2800, whose out-lists exceed the largest hash
+    table: by default its vertices take a block's table as a sorted list; with the hash-only
+    probe they take the global-memory path (checked against the closed form for K_n, which pins
+    the oracle too)."""
+    print(f"[gpu] batch mixed widths + K2800, probe {probe}", flush=True)
     raw = [synth.rmat_scale(11, 16, seed=s) for s in (1, 2, 3)] + [(5000, *synth.er(5000, 40000, seed=4))]
     widths = [4, 8, 4, 8]
     a = np.array(list(itertools.combinations(range(2800), 2)), dtype=np.int32)
-    graphs = [build(ctx, n, s, d, ob) for (n, s, d), ob in zip(raw, widths)]
-    graphs.append(build(ctx, 2800, a[:, 0], a[:, 1], 8))
-    assert graphs[-1].info().global_vertices > 0
-    tris, lccs = outputs(graphs)
-    tk = ctx.batch_submit(graphs, tris, lccs)
-    assert ctx.batch_poll(tk, block=True)[0]
-    for (n, s, d), tri, lcc in zip(raw, tris, lccs):
-        t_ref, l_ref = oracle.tc_lcc(n, s, d)
-        np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
-        assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
-    assert bool((tris[-1] == 2799 * 2798 // 2).all()) and bool((lccs[-1] == 1.0).all())
-    for g in graphs:
-        g.free()
+    probe0 = ctx.tuning().probe
+    ctx.set_tuning(probe=pkg.PROBE_HASH if probe == "hash" else pkg.PROBE_AUTO)
+    try:
+        graphs = [build(ctx, n, s, d, ob) for (n, s, d), ob in zip(raw, widths)]
+        graphs.append(build(ctx, 2800, a[:, 0], a[:, 1], 8))
+        assert (graphs[-1].info().global_vertices > 0) == (probe == "hash")
+        tris, lccs = outputs(graphs)
+        tk = ctx.batch_submit(graphs, tris, lccs)
+        assert ctx.batch_poll(tk, block=True)[0]
+        for (n, s, d), tri, lcc in zip(raw, tris, lccs):
+            t_ref, l_ref = oracle.tc_lcc(n, s, d)
+            np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
+            assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
+        assert bool((tris[-1] == 2799 * 2798 // 2).all()) and bool((lccs[-1] == 1.0).all())
+        for g in graphs:
+            g.free()
+    finally:
+        ctx.set_tuning(probe=probe0)
 
 
 def test_batch_equals_single_runs_and_repeats(ctx):

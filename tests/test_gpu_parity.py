@@ -164,27 +164,21 @@ def clique(n):
 
 
 def test_large_clique_global_path(ctx):
-    """K_2800: |N+(v)| reaches 2799, beyond the largest LDS table (2048 keys), so the
-    global-memory path runs.  Reference: the closed form for K_n (t = C(n-1, 2), LCC = 1),
-    which the oracle's own pins establish; running the oracle on 3.9 M edges would be slow."""
+    """K_2800: |N+(v)| reaches 2799, beyond the largest hash table (2048 keys at load 1/2):
+    by default such vertices take the block table as a sorted list; with the hash-only probe
+    they take the global-memory path.  Reference: the closed form for K_n (t = C(n-1, 2),
+    LCC = 1), which the oracle's own pins establish; running the oracle on 3.9 M edges would be
+    slow."""
     n = 2800
-    say(f"[gpu] K{n} (global path)")
     s, d = clique(n)
-    g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
-    assert g.info().global_vertices > 0, "the clique must take the global-memory path"
-    tri, lcc = g.run()
-    torch.cuda.synchronize()
-    assert bool((tri == (n - 1) * (n - 2) // 2).all())
-    assert bool((lcc == 1.0).all())
-    g.free()
-    # the same clique with 4-byte offsets and the sorted-list probes (a 4096-key table holds
-    # it); the hybrid merges lists of up to 2799 + 2798 entries
     probe0 = ctx.tuning().probe
     try:
-        for probe in (pkg.PROBE_SORTED, pkg.PROBE_MERGE):
-            say(f"[gpu] K{n} probe={probe}")
+        for probe, ob, global_path in [(pkg.PROBE_AUTO, 8, False), (pkg.PROBE_HASH, 8, True),
+                                       (pkg.PROBE_SORTED, 4, False), (pkg.PROBE_MERGE, 4, False)]:
+            say(f"[gpu] K{n} probe={probe} offsets={ob}")
             ctx.set_tuning(probe=probe)
-            g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=4)
+            g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=ob)
+            assert (g.info().global_vertices > 0) == global_path
             tri, lcc = g.run()
             torch.cuda.synchronize()
             assert bool((tri == (n - 1) * (n - 2) // 2).all()) and bool((lcc == 1.0).all())
