@@ -82,49 +82,23 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
     }
 }
 
-// Vertices whose N+(v) exceeds the LDS table: binary search straight in N+(v) in
-// global memory, one wave per in-edge chunk of 64, per-entry counts go to t(w)
-// directly.  Only taken when |N+(v)| exceeds the largest table: 4096 keys (the table as a
-// sorted list), or 2048 with the hash-only probe (4096 slots at load 1/2).
+// Vertices whose N+(v) exceeds the LDS table: one block each, walking the tails in windows as
+// the LDS kernel does, each candidate binary-searched in N+(v) where it lies in HBM (the list
+// stays in the caches while the block works on it) and each hit added to t(w) at once.  Only
+// taken when |N+(v)| exceeds the largest table: 4096 keys (the table as a sorted list), or
+// 2048 with the hash-only probe (4096 slots at load 1/2).
 template <typename OffT>
-__global__ __launch_bounds__(256) void k_count_global(CountArgs<OffT> a) {
+__global__ __launch_bounds__(kCountThreads) void k_count_global(CountArgs<OffT> a) {
     const int w = threadIdx.x / kWave, lane = lane_id();
     for (int64_t it = blockIdx.x; it < a.n_global; it += gridDim.x) {
         const int32_t v = a.vlist[a.n_block + a.n_wave + it];
         const OffT b0 = a.out_off[v];
-        const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
-        const int32_t* nv = a.adj + b0;
-        const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
+        Table tb;
+        tb.keys = const_cast<int32_t*>(a.adj + b0);
+        tb.T = (int32_t)(a.out_off[v + 1] - b0);
+        tb.tg = a.t;
         unsigned long long local = 0;
-        for (OffT cb = i0 + (OffT)w * kWave; cb < i1; cb += (OffT)4 * kWave) {
-            const OffT k = cb + lane;
-            const bool ok = k < i1;
-            int32_t u = 0;
-            OffT st = 0;
-            int32_t len = 0;
-            if (ok) {
-                u = a.in_u[k];
-                st = a.in_start[k];
-                len = a.in_len[k];
-            }
-            // each lane walks its own tail (rare path, kept simple)
-            uint32_t hits = 0;
-            for (int32_t j = 0; j < len; ++j) {
-                const int32_t x = a.adj[st + j];
-                int lo = 0, hi = dv;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (nv[mid] < x) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo < dv && nv[lo] == x) {
-                    atomicAdd(&a.t[x], 1ull);
-                    ++hits;
-                }
-            }
-            if (hits) atomicAdd(&a.t[u], (unsigned long long)hits);
-            local += hits;
-        }
+        walk_tails<OffT, kProbeGlobal, kWavesPerBlock>(a, v, tb, w, local);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
     }
@@ -200,7 +174,7 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, int merge_x100, int spare_per_
         CountArgs<OffT> ag = a;
         ag.vlist = d.vlist + d.n_list;  // k_count_global reads past the block and wave vertices
         const unsigned grid = (unsigned)std::min<int64_t>(d.n_global, (int64_t)g->ctx->cu_count * 4);
-        k_count_global<OffT><<<grid, 256, 0, st>>>(ag);
+        k_count_global<OffT><<<grid, kCountThreads, 0, st>>>(ag);
         TCL_HIP(hipGetLastError());
     }
     return TC_LCC_OK;

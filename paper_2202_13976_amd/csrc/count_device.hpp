@@ -98,9 +98,14 @@ struct Win {
 //           index in N+(v) of the word's first entry, plus one zero guard word; cnt[dv].
 //           The entry index of a hit is first + popcount of the bits below it; candidates
 //           outside the range clamp onto the guard word.  One 8-byte LDS read per probe.
+// Probe mode of lists longer than any LDS table: binary search in N+(v) where it lies in HBM,
+// each hit added to t(w) at once (not a value of the public probe enum).
+constexpr int kProbeGlobal = 16;
+
 struct Table {
     int32_t* keys;
     uint32_t* cnt;
+    unsigned long long* tg;  // global mode: t
     uint32_t* bm;
     int32_t T;
     uint32_t nb_mask;
@@ -146,6 +151,9 @@ __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) 
             if (!__ballot(pending)) break;
             b = pending ? ((b + 1) & tb.nb_mask) : b;
         }
+    } else if constexpr (MODE == kProbeGlobal) {
+        hit = val && sorted_find(tb.keys, tb.T, x) >= 0;
+        if (hit) atomicAdd(&tb.tg[x], 1ull);
     } else {
         const int sl = sorted_find(tb.keys, tb.T, x);
         hit = val && sl >= 0;

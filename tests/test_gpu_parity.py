@@ -187,6 +187,21 @@ def test_large_clique_global_path(ctx):
         ctx.set_tuning(probe=probe0)
 
 
+def test_clique_beyond_every_table(ctx):
+    """K_4500: |N+(v)| reaches 4499, beyond the LDS table even as a sorted list (4096 keys), so
+    the default probe sends ranks 1..402 to the global-memory path (rank 0 has no in-edge, so
+    no work).  Reference: the closed form for K_n."""
+    n = 4500
+    say(f"[gpu] K{n} (global path under the default probe)")
+    s, d = (x.astype(np.int32) for x in np.triu_indices(n, 1))
+    g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    assert g.info().global_vertices == n - 2 - 4096
+    tri, lcc = g.run()
+    torch.cuda.synchronize()
+    assert bool((tri == (n - 1) * (n - 2) // 2).all()) and bool((lcc == 1.0).all())
+    g.free()
+
+
 def test_host_inputs_and_repeats(ctx):
     n, s, d = synth.rmat_scale(12, 16, seed=77)
     t_ref = check(ctx, n, s, d, "host inputs", host=True)
