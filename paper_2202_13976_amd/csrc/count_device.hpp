@@ -288,10 +288,12 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
                             // two ballots of plain compares, combined in scalar registers
                             const unsigned long long H =
                                 __builtin_amdgcn_ballot_w64(in_tail) & __builtin_amdgcn_ballot_w64(set);
-                            if (in_tail && set) {
-                                const uint32_t pos = (uint32_t)__popc(__builtin_amdgcn_ubfe(wd[q], 0u, ii[q])) + fs[q];
-                                atomicAdd((uint32_t*)((char*)tb.cnt + (pos << 2)), 1u);
-                            }
+                            // every lane adds 1: a hit to its entry's counter, any other lane to
+                            // a spare word of its own after the counters (no exec-mask change)
+                            const uint32_t pos = (in_tail && set)
+                                                     ? (uint32_t)__popc(__builtin_amdgcn_ubfe(wd[q], 0u, ii[q])) + fs[q]
+                                                     : (uint32_t)tb.T + (uint32_t)lane;
+                            atomicAdd((uint32_t*)((char*)tb.cnt + (pos << 2)), 1u);
                             account(js[sl], H);
                         }
                         xs[sl] = gen(js[sl], lims[sl]);
@@ -418,9 +420,10 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
     }
 }
 
-// Bytes of the bitmap layout for `words` bitmap words (plus the guard word) and dv counters.
+// Bytes of the bitmap layout for `words` bitmap words (plus the guard word), dv counters and
+// one spare word per lane.
 __host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
-    return 8u * (words + 1u) + 4u * (uint32_t)dv;
+    return 8u * (words + 1u) + 4u * (uint32_t)dv + 4u * kWave;
 }
 
 // One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
@@ -450,7 +453,8 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
     // ---- stage N+(v)
     if (mode == TC_LCC_PROBE_BITMAP) {
         tb.bm = (uint32_t*)region;
-        tb.cnt = (uint32_t*)(region + 8u * (tb.words + 1u));
+        tb.cnt = (uint32_t*)(region + 8u * (tb.words + 1u));  // dv counters, then 64 spare words
+        tb.T = dv;
         for (uint32_t s = gtid; s <= tb.words; s += gsize) tb.bm[2 * s] = 0u;  // with the guard word
         for (int j = gtid; j < dv; j += gsize) tb.cnt[j] = 0u;
         group_sync<NWAVES>();
