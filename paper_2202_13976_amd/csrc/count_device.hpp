@@ -183,16 +183,25 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
     const uint32_t lane4 = (uint32_t)lane * 4u;
     wig = __builtin_amdgcn_readfirstlane(wig);  // wave-uniform: keeps the generator scalar
     const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
+    // the in-edges of the next chunk are loaded while this one is walked
+    int32_t nu = 0;
+    OffT nst = 0;
+    int32_t nlen = 0;
+    if (i0 + lane < i1) {
+        nu = a.in_u[i0 + lane];
+        nst = a.in_start[i0 + lane];
+        nlen = a.in_len[i0 + lane];
+    }
     for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
         const OffT k = cb + lane;
         const bool ok = k < i1;
-        int32_t u = 0;
-        OffT st = 0;
-        int32_t len = 0;
-        if (ok) {
-            u = a.in_u[k];
-            st = a.in_start[k];
-            len = a.in_len[k];
+        const int32_t u = nu;
+        const OffT st = nst;
+        const int32_t len = nlen;
+        if (k + kWave < i1) {
+            nu = a.in_u[k + kWave];
+            nst = a.in_start[k + kWave];
+            nlen = a.in_len[k + kWave];
         }
         const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
         uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
