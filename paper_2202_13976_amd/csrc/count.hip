@@ -67,12 +67,23 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
     for (int64_t it = ((grid - 1 - blockIdx.x) * (int64_t)kWavesPerBlock + w) * grab;;) {
         if (it >= a.n_wave) break;
         const int64_t end = min(it + (int64_t)grab, a.n_wave);
-        for (; it < end; ++it) {
-            const int32_t v = a.vlist[a.n_block + it];
+        // the grab's vertices and their list bounds, lane q holding vertex it + q, loaded at once
+        int32_t hv = 0;
+        OffT hb0 = 0, hb1 = 0, hi0 = 0, hi1 = 0;
+        if (it + lane < end) {
+            hv = a.vlist[a.n_block + it + lane];
+            hb0 = a.out_off[hv];
+            hb1 = a.out_off[hv + 1];
+            hi0 = a.in_off[hv];
+            hi1 = a.in_off[hv + 1];
+        }
+        for (int q = 0; it < end; ++it, ++q) {
+            const VertexHead<OffT> hd{__builtin_amdgcn_readlane(hv, q), lane_value(hb0, q), lane_value(hb1, q),
+                                      lane_value(hi0, q), lane_value(hi1, q)};
             unsigned long long local = 0;
-            process_vertex<OffT, PROBE, 1>(a, v, wregion, wave_bytes, lane, 0, local);
+            process_vertex<OffT, PROBE, 1>(a, hd, wregion, wave_bytes, lane, 0, local);
             const unsigned long long ws = wave_sum(local);
-            if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
+            if (lane == 0 && ws) atomicAdd(&a.t[hd.v], ws);
         }
         if (waves * grab >= a.n_wave) break;
         unsigned int q = 0;
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_global(CountArgs<OffT> 
         tb.T = (int32_t)(a.out_off[v + 1] - b0);
         tb.tg = a.t;
         unsigned long long local = 0;
-        walk_tails<OffT, kProbeGlobal, kWavesPerBlock>(a, v, tb, w, local);
+        walk_tails<OffT, kProbeGlobal, kWavesPerBlock>(a, first_in_edges<kWavesPerBlock>(a, v, w), tb, w, local);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
     }

@@ -162,11 +162,44 @@ __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) 
     return hit;
 }
 
+// v's in-edge range and this lane's in-edge of the wave's first chunk (u, tail start, tail
+// length), loaded as soon as v is known so that they arrive while N+(v) is staged.  Wave wig of
+// NWAVES takes in-edges i0 + wig, i0 + wig + NWAVES, ...: lane l of a chunk holds the l-th.
+template <typename OffT>
+struct InEdges {
+    OffT i0, i1;
+    int32_t u;
+    OffT st;
+    int32_t len;
+};
+
+template <int NWAVES, typename OffT>
+__device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a, OffT i0, OffT i1, int wig) {
+    InEdges<OffT> e;
+    e.i0 = i0;
+    e.i1 = i1;
+    e.u = 0;
+    e.st = 0;
+    e.len = 0;
+    const OffT k = e.i0 + (OffT)lane_id() * NWAVES + wig;
+    if (k < e.i1) {
+        e.u = a.in_u[k];
+        e.st = a.in_start[k];
+        e.len = a.in_len[k];
+    }
+    return e;
+}
+
+template <int NWAVES, typename OffT>
+__device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a, int32_t v, int wig) {
+    return first_in_edges<NWAVES>(a, a.in_off[v], a.in_off[v + 1], wig);
+}
+
 // The waves of a group walk the tails of v's in-edges, 64 in-edges (a chunk) at a time,
 // and probe every candidate in windows of 64 consecutive candidates of one tail.  Wave
-// wig of NWAVES takes tails wig, wig + NWAVES, ... of every chunk, so the waves of a
-// block share each vertex evenly whatever its in-degree, and every tail stays with one
-// wave.
+// wig of NWAVES takes in-edges wig, wig + NWAVES, ... (its chunks hold every NWAVES-th
+// in-edge), so the waves of a block share each vertex evenly whatever its in-degree, and
+// every tail stays with one wave.
 //
 // The window generator's state is wave-uniform (tail j is owned by lane j; the tail's
 // start pointer is formed once per tail), so a window costs a few scalar operations.  A
@@ -176,34 +209,33 @@ __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) 
 // found here is a triangle with v as its middle vertex, so the hits are also v's share
 // (`local`).
 template <typename OffT, int MODE, int NWAVES>
-__device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb, int wig,
+__device__ void walk_tails(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb, int wig,
                            unsigned long long& local) {
     constexpr int kRing = 2 * kUnroll;
     const int lane = lane_id();
     const uint32_t lane4 = (uint32_t)lane * 4u;
     wig = __builtin_amdgcn_readfirstlane(wig);  // wave-uniform: keeps the generator scalar
-    const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
+    const OffT i0 = ie.i0, i1 = ie.i1;
     // the in-edges of the next chunk are loaded while this one is walked
-    int32_t nu = 0;
-    OffT nst = 0;
-    int32_t nlen = 0;
-    if (i0 + lane < i1) {
-        nu = a.in_u[i0 + lane];
-        nst = a.in_start[i0 + lane];
-        nlen = a.in_len[i0 + lane];
-    }
-    for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
-        const OffT k = cb + lane;
+    int32_t nu = ie.u;
+    OffT nst = ie.st;
+    int32_t nlen = ie.len;
+    constexpr OffT kSpan = (OffT)kWave * NWAVES;  // in-edges a chunk of the group covers
+    for (OffT cb = i0; cb < i1; cb += kSpan) {
+        const OffT k = cb + (OffT)lane * NWAVES + wig;
         const bool ok = k < i1;
         const int32_t u = nu;
         const OffT st = nst;
         const int32_t len = nlen;
-        if (k + kWave < i1) {
-            nu = a.in_u[k + kWave];
-            nst = a.in_start[k + kWave];
-            nlen = a.in_len[k + kWave];
+        if (k + kSpan < i1) {
+            nu = a.in_u[k + kSpan];
+            nst = a.in_start[k + kSpan];
+            nlen = a.in_len[k + kSpan];
         }
-        const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
+        // lanes of this wave holding an in-edge of the chunk
+        const OffT rest = i1 - cb - wig;
+        const int nk = (int)__builtin_amdgcn_readfirstlane(
+            rest <= 0 ? 0 : (int)min((OffT)kWave, (rest + NWAVES - 1) / NWAVES));
         uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
         // this lane's tail as a byte offset into adj and a byte length, formed once per chunk
         // (the tail pointer is adj plus the offset, so loads stay in the global address space)
@@ -237,11 +269,11 @@ __device__ void walk_tails(const CountArgs<OffT>& a, int32_t v, const Table& tb,
             gbase4 += kWave * 4;
             if (gbase4 >= gend4) {
                 gbase4 = 0;
-                gj += NWAVES;
+                gj += 1;
                 fetch_tail();
             }
         };
-        gj = wig;
+        gj = 0;
         fetch_tail();
         // next window of this wave: its tail j, the bytes of candidates from the window on
         // (lanes with lane4 >= lim hold none), and this lane's candidate (lanes past the tail
@@ -439,13 +471,27 @@ __host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_
 // wig = wave index in the group) with an LDS region of region_bytes.  The probe method is
 // chosen per vertex: the rank bitmap when it fits (AUTO or BITMAP), else the hash; or the
 // sorted list (binary search per candidate, or the hybrid of Eq. 3) when asked for.  Returns this lane's share of t(v) in `local`.
+// A vertex with the bounds of its out-list and in-edge list.
+template <typename OffT>
+struct VertexHead {
+    int32_t v;
+    OffT b0, b1, i0, i1;
+};
+
+template <typename OffT>
+__device__ __forceinline__ VertexHead<OffT> vertex_head(const CountArgs<OffT>& a, int32_t v) {
+    return VertexHead<OffT>{v, a.out_off[v], a.out_off[v + 1], a.in_off[v], a.in_off[v + 1]};
+}
+
 template <typename OffT, int PROBE, int NWAVES>
-__device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region, uint32_t region_bytes,
-                               int gtid, int wig, unsigned long long& local) {
+__device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>& hd, uint8_t* region,
+                               uint32_t region_bytes, int gtid, int wig, unsigned long long& local) {
     constexpr int gsize = NWAVES * kWave;
-    const OffT b0 = a.out_off[v];
-    const int32_t dv = (int32_t)(a.out_off[v + 1] - b0);
+    const int32_t v = hd.v;
+    const OffT b0 = hd.b0;
+    const int32_t dv = (int32_t)(hd.b1 - b0);
     const int32_t* nv = a.adj + b0;
+    const InEdges<OffT> ie = first_in_edges<NWAVES>(a, hd.i0, hd.i1, __builtin_amdgcn_readfirstlane(wig));
 
     Table tb;
     tb.base = v + 1;
@@ -498,10 +544,10 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
     group_sync<NWAVES>();
 
     // ---- probe the tails of the in-edges
-    if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, v, tb, wig, local);
-    else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, v, tb, wig, local);
+    if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, wig, local);
+    else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, wig, local);
     else if (mode == TC_LCC_PROBE_MERGE) walk_tails_hybrid<OffT, NWAVES>(a, v, tb, wig, local);
-    else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, v, tb, wig, local);
+    else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, ie, tb, wig, local);
     group_sync<NWAVES>();
 
     // ---- flush the per-entry counters of N+(v)
@@ -517,6 +563,12 @@ __device__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* reg
         }
     }
     group_sync<NWAVES>();
+}
+
+template <typename OffT, int PROBE, int NWAVES>
+__device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region,
+                                               uint32_t region_bytes, int gtid, int wig, unsigned long long& local) {
+    process_vertex<OffT, PROBE, NWAVES>(a, vertex_head(a, v), region, region_bytes, gtid, wig, local);
 }
 
 }  // namespace tcl
