@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -62,12 +63,21 @@ def survey_bytes(info) -> int:
 COUNT_SOURCES = ("count.hip", "count_device.hpp", "common.hpp", "internal.hpp")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank lines (an edit of a comment leaves the kernel as
+    it was).  String literals in these sources hold no comment markers."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*", "", line).rstrip() for line in text.splitlines()]
+    return "\n".join(line for line in lines if line.strip())
+
+
 def count_source_sha() -> str:
-    """SHA-256 over the sources that define the count kernel, in a fixed order."""
+    """SHA-256 over the code (comments dropped) of the sources that define the count kernel, in
+    a fixed order."""
     h = hashlib.sha256()
     for name in COUNT_SOURCES:
-        with open(os.path.join(ROOT, "paper_2202_13976_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2202_13976_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

@@ -9,7 +9,8 @@
 //
 // Scatter (each triangle adds 1 to t(u), t(v), t(w); Alg. 3 accumulates t):
 //   t(v): summed in registers, one atomic per wave and vertex;
-//   t(u): one LDS counter per in-edge, one global atomic per in-edge that closed any;
+//   t(u): counted in the register lane that holds the in-edge, one global atomic per
+//         in-edge that closed any;
 //   t(w): one LDS counter per entry of N+(v), one global atomic per entry that hit.
 // So there are at most 2m + n global atomics whatever the triangle count.
 //
@@ -19,11 +20,14 @@
 // of every block (and the first grab of every wave) is fixed by its index and only
 // later ones come from the queue counter: device-wide atomics on one address are
 // serialized, so a small graph runs without any and a large one needs few.
-// Each wave takes 64 in-edges at a
-// time and walks their tails one after the other in windows of 64 candidates
-// (lane i reads candidate base + i: coalesced), with all loop bounds wave-uniform
-// (scalar).  A ring of kUnroll windows is prefetched, so that many loads stay in
-// flight across tail boundaries.  Hits per tail are popcounts of ballots.
+// Each wave takes 64 of its in-edges at a time (in a block, every fourth in-edge of the
+// vertex) and walks their tails one after the other in windows of 64 candidates (lane i
+// reads candidate base + i: coalesced), with all loop bounds wave-uniform (scalar).  A ring
+// of 2 * kUnroll windows is prefetched, so that many loads stay in flight across tail
+// boundaries, and the next 64 in-edges are loaded while these are walked.  Hits per tail
+// are popcounts of ballots.  Block vertices whose N+(v) is too long for the hash take the
+// table as a sorted list in a launch of their own; lists beyond the table are searched in
+// HBM (k_count_global).
 #include "count_device.hpp"
 
 namespace tcl {
