@@ -385,12 +385,23 @@ struct EdgePay {
     int32_t len;
 };
 
+// Layout of the word by which the in-edges are sorted: the key (v, or 2^bits for an edge that
+// cannot close a triangle) at bit vshift and up, under it either u and the edge's position in
+// N+(u) (packed: u << pbits | position; vshift = 64 minus the key's digit passes) or, where
+// those do not fit, the edge index with the rest in an 8-byte payload array (vshift = 32).
+struct InWord {
+    int vshift;
+    int pbits;
+    bool packed;
+    __host__ __device__ uint64_t low_mask() const { return (1ull << vshift) - 1; }
+};
+
 // Per oriented edge i = (u -> v) at position i of N+(u) (its tail is adj[i+1 .. out_off[u+1])):
-// the adjacency entry, the payload, and the word (v, i) by which the in-edges are sorted.
+// the adjacency entry and the in-edge word (with the payload where the word cannot hold it).
 // An edge that cannot close a triangle (empty tail, or N+(v) empty) gets the key 2^bits,
 // above every vertex, so it sorts after all in-edges that are kept.
 template <typename OffT>
-__global__ __launch_bounds__(kB) void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits,
+__global__ __launch_bounds__(kB) void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits, InWord iw,
                                                   const OffT* __restrict__ out_off, const int32_t* __restrict__ dplus,
                                                   int32_t* __restrict__ adj, uint64_t* __restrict__ words,
                                                   EdgePay* __restrict__ pay, uint32_t* __restrict__ hist) {
@@ -404,17 +415,25 @@ __global__ __launch_bounds__(kB) void k_edge_emit(const uint64_t* __restrict__ o
         adj[i] = (int32_t)v;
         const int64_t len = (int64_t)out_off[u + 1] - (int64_t)i - 1;
         const bool kept = len > 0 && dplus[v] > 0;
-        const uint64_t w = ((kept ? (uint64_t)v : (1ull << bits)) << 32) | (uint64_t)i;
+        const uint64_t key = kept ? (uint64_t)v : (1ull << bits);
+        uint64_t w;
+        if (iw.packed) {
+            const uint64_t pos = (uint64_t)((int64_t)i - (int64_t)out_off[u]);
+            w = (key << iw.vshift) | ((uint64_t)u << iw.pbits) | pos;
+        } else {
+            w = (key << iw.vshift) | (uint64_t)i;
+            pay[i] = EdgePay{(int32_t)u, (int32_t)len};
+        }
         words[i] = w;
-        pay[i] = EdgePay{(int32_t)u, (int32_t)len};
-        dc.add(w, 32, passes);
+        dc.add(w, iw.vshift, passes);
     }
     dc.flush(hist, passes);
 }
 
 // Number of leading words whose key is below 2^bits (the kept in-edges), by bisection.
-__global__ void k_count_kept(const uint64_t* __restrict__ words, size_t m, int bits, uint32_t* __restrict__ out) {
-    const uint64_t cut = (1ull << bits) << 32;
+__global__ void k_count_kept(const uint64_t* __restrict__ words, size_t m, int bits, int vshift,
+                             uint32_t* __restrict__ out) {
+    const uint64_t cut = (1ull << bits) << vshift;
     size_t lo = 0, hi = m;
     while (lo < hi) {
         const size_t mid = (lo + hi) >> 1;
@@ -424,33 +443,47 @@ __global__ void k_count_kept(const uint64_t* __restrict__ words, size_t m, int b
     *out = (uint32_t)lo;
 }
 
-// In-edge k (sorted by v, then by edge index, so by u): its edge index is the word's low half.
+// In-edge k (sorted by v, then by edge position, so by u): u, its tail's start and length, from
+// the packed word and the row bounds of u, or from the payload of the word's edge index.
 // Also work[v] = sum of the tail lengths of v's in-edges (zeroed by the caller): lanes of a wave
 // hold consecutive k, so each run of equal v within the wave is summed by a scan and added with
 // one atomic by its last lane.
 template <typename OffT>
-__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, const EdgePay* __restrict__ pay,
-                          int32_t* __restrict__ in_u, OffT* __restrict__ in_start, int32_t* __restrict__ in_len,
-                          unsigned long long* __restrict__ work) {
+__global__ void k_in_fill(const uint64_t* __restrict__ words, size_t kept, InWord iw, const OffT* __restrict__ out_off,
+                          const EdgePay* __restrict__ pay, int32_t* __restrict__ in_u, OffT* __restrict__ in_start,
+                          int32_t* __restrict__ in_len, unsigned long long* __restrict__ work) {
     const int lane = lane_id();
     GRID_STRIDE(k, kept) {
         const uint64_t wd = words[k];
-        const uint32_t i = (uint32_t)(wd & 0xffffffffull);
-        const uint32_t v = (uint32_t)(wd >> 32);
-        const EdgePay e = pay[i];
-        in_u[k] = e.u;
-        in_start[k] = (OffT)i + 1;
-        in_len[k] = e.len;
+        const uint32_t v = (uint32_t)(wd >> iw.vshift);
+        const uint64_t low = wd & iw.low_mask();
+        int32_t u, len;
+        OffT start;
+        if (iw.packed) {
+            u = (int32_t)(low >> iw.pbits);
+            const OffT pos = (OffT)(low & ((1ull << iw.pbits) - 1));
+            const OffT o0 = out_off[u], o1 = out_off[u + 1];
+            start = o0 + pos + 1;
+            len = (int32_t)(o1 - start);
+        } else {
+            const EdgePay e = pay[low];
+            u = e.u;
+            start = (OffT)low + 1;
+            len = e.len;
+        }
+        in_u[k] = u;
+        in_start[k] = start;
+        in_len[k] = len;
         // lanes past the end are inactive; lane l's run starts at the last head at or below l
         const uint32_t vp = (uint32_t)__shfl_up((int)v, 1, kWave);
         const uint32_t vn = (uint32_t)__shfl_down((int)v, 1, kWave);
         const bool head = lane == 0 || vp != v;
         const bool tail = lane == kWave - 1 || k + 1 == kept || vn != v;
-        const unsigned long long incl = wave_inclusive_scan((unsigned long long)(uint32_t)e.len);
+        const unsigned long long incl = wave_inclusive_scan((unsigned long long)(uint32_t)len);
         const unsigned long long heads = __builtin_amdgcn_ballot_w64(head);
-        const int start = 63 - __builtin_clzll(heads & (~0ull >> (kWave - 1 - lane)));
-        const unsigned long long before = __shfl(incl, start > 0 ? start - 1 : 0, kWave);
-        if (tail) atomicAdd(&work[v], incl - (start > 0 ? before : 0ull));
+        const int start_lane = 63 - __builtin_clzll(heads & (~0ull >> (kWave - 1 - lane)));
+        const unsigned long long before = __shfl(incl, start_lane > 0 ? start_lane - 1 : 0, kWave);
+        if (tail) atomicAdd(&work[v], incl - (start_lane > 0 ? before : 0ull));
     }
 }
 
@@ -699,6 +732,7 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, n, d.dplus);
     TCL_HIP(hipGetLastError());
     TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{d.dplus, n}, N + 1, out_off, scanO, st));
+    int dmax = 0;  // longest row of N+
     if (m > 0) {
         int* mx = bad + 4;
         k_max_i32<<<grid_for(N, kB, 1024), kB, 0, st>>>(d.dplus, n, mx);
@@ -710,7 +744,6 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         TCL_TRY(tmp.get(N + 1, &rpos2));
         TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n, kWave}, N + 1, rpos, scan32, st));
         TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n, kMid}, N + 1, rpos2, scan32, st));
-        int dmax = 0;
         uint32_t nlong = 0, nlong2 = 0;
         TCL_HIP(hipMemcpyAsync(&dmax, mx, sizeof(int), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipMemcpyAsync(&nlong, rpos + N, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -757,15 +790,23 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     uint32_t kept = 0;
     EdgePay* pay = nullptr;
     uint64_t* ws = wa;
-    TCL_TRY(tmp.get(std::max<size_t>(m, 1), &pay));
+    // the in-edge word: u and the row position packed under the key when they fit
+    InWord iw;
+    iw.pbits = dmax > 1 ? ceil_log2((uint64_t)dmax) : 0;
+    iw.vshift = 64 - 8 * digit_passes(bits + 1);
+    iw.packed = bits + iw.pbits <= iw.vshift;
+    if (!iw.packed) {
+        iw.vshift = 32;
+        TCL_TRY(tmp.get(std::max<size_t>(m, 1), &pay));
+    }
     if (m > 0) {
         TCL_HIP(radix_counts_clear(sort_scratch, st));
-        k_edge_emit<OffT><<<grid_for(m, kB, 1024), kB, 0, st>>>(osorted, m, bits, out_off, d.dplus, d.adj, wa, pay,
-                                                                radix_counts(sort_scratch));
+        k_edge_emit<OffT><<<grid_for(m, kB, 1024), kB, 0, st>>>(osorted, m, bits, iw, out_off, d.dplus, d.adj, wa,
+                                                                pay, radix_counts(sort_scratch));
         TCL_HIP(hipGetLastError());
-        TCL_HIP(radix_sort_u64(wa, wb, m, 32, bits + 1, sort_scratch, sort_err, st, &ws, true));
+        TCL_HIP(radix_sort_u64(wa, wb, m, iw.vshift, bits + 1, sort_scratch, sort_err, st, &ws, true));
         uint32_t* kc_dev = (uint32_t*)(bad + 5);
-        k_count_kept<<<1, 1, 0, st>>>(ws, m, bits, kc_dev);
+        k_count_kept<<<1, 1, 0, st>>>(ws, m, bits, iw.vshift, kc_dev);
         TCL_HIP(hipGetLastError());
         TCL_HIP(hipMemcpyAsync(&kept, kc_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         TCL_HIP(hipStreamSynchronize(st));
@@ -781,15 +822,15 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     TCL_TRY(keep(g, N + 1, &in_off));
     d.in_off = in_off;
     TCL_TRY(keep(g, N, &d.work));
-    TCL_HIP(run_bounds(GroupShift{ws, 32}, kept, f2, l2, n, st));
+    TCL_HIP(run_bounds(GroupShift{ws, iw.vshift}, kept, f2, l2, n, st));
     int32_t* din = deg;  // degrees by vertex are not needed any more (deg_r keeps them by rank)
     k_run_counts<<<grid_for(N, kB, 8192), kB, 0, st>>>(f2, l2, n, din);
     TCL_HIP(hipGetLastError());
     TCL_HIP(exclusive_scan<OffT>(I32In<OffT>{din, n}, N + 1, in_off, scanO, st));
     TCL_HIP(fill<uint64_t>(d.work, N, 0ull, st));
     if (kept > 0) {
-        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, pay, d.in_u, in_start, d.in_len,
-                                                                 (unsigned long long*)d.work);
+        k_in_fill<OffT><<<grid_for(kept, kB, 8192), kB, 0, st>>>(ws, kept, iw, out_off, pay, d.in_u, in_start,
+                                                                 d.in_len, (unsigned long long*)d.work);
         TCL_HIP(hipGetLastError());
     }
 
