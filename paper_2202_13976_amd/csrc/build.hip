@@ -119,16 +119,42 @@ struct GroupShift {
     __device__ uint32_t operator()(size_t i) const { return (uint32_t)(k[i] >> shift); }
 };
 
-struct Group32 {
-    const uint32_t* k;
-    __device__ uint32_t operator()(size_t i) const { return k[i]; }
-};
-
-// deg[v] = (lo-side run length) + (hi-side run length)
+// deg[v] = (lo-side run length) + (hi-side count)
 __global__ void k_degrees(const uint32_t* __restrict__ f1, const uint32_t* __restrict__ l1,
-                          const uint32_t* __restrict__ f2, const uint32_t* __restrict__ l2, int64_t n,
-                          int32_t* __restrict__ deg) {
-    GRID_STRIDE(v, n) deg[v] = (int32_t)((l1[v] - f1[v]) + (l2[v] - f2[v]));
+                          const uint32_t* __restrict__ hi_count, int64_t n, int32_t* __restrict__ deg) {
+    GRID_STRIDE(v, n) deg[v] = (int32_t)((l1[v] - f1[v]) + hi_count[v]);
+}
+
+// Hi-side counts from the hi ends sorted by their bits above kBucketBits: block b counts the
+// ends in [b << kBucketBits, (b + 1) << kBucketBits) in LDS (many ends of one vertex only
+// contend in LDS) and writes the counts of its range, which no other block touches.
+constexpr int kBucketBits = 15;  // 32768 counters, 128 KiB of LDS
+constexpr int kBucketThreads = 1024;
+
+__device__ __forceinline__ size_t lower_bound_u32(const uint32_t* a, size_t n, uint64_t x) {
+    size_t lo = 0, hi = n;
+    while (lo < hi) {
+        const size_t mid = (lo + hi) >> 1;
+        if ((uint64_t)a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_counts(const uint32_t* __restrict__ ends, size_t m,
+                                                                  int64_t n, uint32_t* __restrict__ count) {
+    __shared__ uint32_t c[1u << kBucketBits];
+    __shared__ size_t range[2];
+    const uint64_t b0 = (uint64_t)blockIdx.x << kBucketBits;
+    for (int i = threadIdx.x; i < (1 << kBucketBits); i += blockDim.x) c[i] = 0;
+    if (threadIdx.x < 2) range[threadIdx.x] = lower_bound_u32(ends, m, b0 + ((uint64_t)threadIdx.x << kBucketBits));
+    __syncthreads();
+    const size_t e0 = range[0], e1 = range[1];
+    for (size_t i = e0 + threadIdx.x; i < e1; i += blockDim.x)
+        atomicAdd(&c[ends[i] & ((1u << kBucketBits) - 1)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < (1 << kBucketBits); i += blockDim.x)
+        if ((int64_t)(b0 + i) < n) count[b0 + i] = c[i];
 }
 
 __global__ void k_rank_keys(const int32_t* __restrict__ deg, int64_t n, int bits, uint64_t* __restrict__ rk) {
@@ -685,15 +711,21 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         return TC_LCC_INVALID_ARGUMENT;
     }
     uint64_t* spare = (ukeys == ka) ? kb : ka;  // held the raw sorted keys, free from here on
-    // degrees: lo ends are runs of the (lo, hi)-sorted unique keys; hi ends are runs after a
-    // sort of the 32-bit hi ends
+    // degrees: lo ends are runs of the (lo, hi)-sorted unique keys; hi ends are counted per
+    // 2^15-vertex range in LDS after a sort of the 32-bit hi ends by their bits above that
+    // (one pass at 2^23 vertices)
     TCL_HIP(run_bounds(GroupShift{ukeys, bits}, m, f1, l1, n, st));
+    uint32_t* hi_count = f2;
     {
         uint32_t* hs = (uint32_t*)kc;
-        if (m > 0) TCL_HIP(radix_sort_u32((uint32_t*)kc, (uint32_t*)spare, m, 0, bits, sort_scratch, sort_err, st, &hs));
-        TCL_HIP(run_bounds(Group32{hs}, m, f2, l2, n, st));
+        if (m > 0 && bits > kBucketBits)
+            TCL_HIP(radix_sort_u32((uint32_t*)kc, (uint32_t*)spare, m, kBucketBits, bits - kBucketBits, sort_scratch,
+                                   sort_err, st, &hs));
+        const size_t buckets = ((size_t)n + (1u << kBucketBits) - 1) >> kBucketBits;
+        k_bucket_counts<<<(unsigned)buckets, kBucketThreads, 0, st>>>(hs, m, n, hi_count);
+        TCL_HIP(hipGetLastError());
     }
-    k_degrees<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, f2, l2, n, deg);
+    k_degrees<<<grid_for(N, kB, 8192), kB, 0, st>>>(f1, l1, hi_count, n, deg);
     TCL_HIP(hipGetLastError());
 
     mark(d, 1, st);
