@@ -103,13 +103,42 @@ __global__ __launch_bounds__(kScanThreads) void k_unique_tiles(const uint64_t* _
 }
 
 // Run boundaries of a sorted array grouped by g(i): first[g] = start, last[g] = one past the
-// end.  Groups that do not occur keep the zeros the caller stored.
+// end.  Groups that do not occur keep the zeros the caller stored.  A wave takes kBoundItems
+// rows of 64 consecutive entries at a time, all loads in flight at once; an entry's neighbours
+// come from the lanes beside it, across rows from the edge lanes, and past the wave's span from
+// one extra load on each side.
+constexpr int kBoundItems = 4;
+
 template <typename G>
 __global__ void k_run_bounds(G g, size_t N, uint32_t* __restrict__ first, uint32_t* __restrict__ last) {
-    GRID_STRIDE(i, N) {
-        const uint32_t gi = g(i);
-        if (i == 0 || g(i - 1) != gi) first[gi] = (uint32_t)i;
-        if (i + 1 == N || g(i + 1) != gi) last[gi] = (uint32_t)(i + 1);
+    const int lane = lane_id();
+    const size_t span = (size_t)kBoundItems * kWave;
+    const size_t wpb = blockDim.x / kWave;
+    const size_t stride = (size_t)gridDim.x * wpb * span;
+    for (size_t b = (blockIdx.x * wpb + threadIdx.x / kWave) * span; b < N; b += stride) {
+        uint32_t gv[kBoundItems];
+#pragma unroll
+        for (int q = 0; q < kBoundItems; ++q) {
+            const size_t i = b + (size_t)q * kWave + lane;
+            gv[q] = g(i < N ? i : N - 1);
+        }
+        const uint32_t before = b > 0 ? g(b - 1) : 0u;
+        const uint32_t after = b + span < N ? g(b + span) : 0u;
+#pragma unroll
+        for (int q = 0; q < kBoundItems; ++q) {
+            const size_t i = b + (size_t)q * kWave + lane;
+            const uint32_t left = q > 0 ? (uint32_t)__builtin_amdgcn_readlane(gv[q > 0 ? q - 1 : 0], kWave - 1) : before;
+            const uint32_t right =
+                q + 1 < kBoundItems ? (uint32_t)__builtin_amdgcn_readlane(gv[q + 1 < kBoundItems ? q + 1 : q], 0) : after;
+            uint32_t prev = __shfl_up(gv[q], 1, kWave);
+            uint32_t next = __shfl_down(gv[q], 1, kWave);
+            if (lane == 0) prev = left;
+            if (lane == kWave - 1) next = right;
+            if (i < N) {
+                if (i == 0 || prev != gv[q]) first[gv[q]] = (uint32_t)i;
+                if (i + 1 == N || next != gv[q]) last[gv[q]] = (uint32_t)(i + 1);
+            }
+        }
     }
 }
 
@@ -623,7 +652,7 @@ hipError_t run_bounds(G g, size_t N, uint32_t* first, uint32_t* last, int64_t n,
     hipError_t e = fill<uint32_t>(first, (size_t)n, 0u, st);
     if (e == hipSuccess) e = fill<uint32_t>(last, (size_t)n, 0u, st);
     if (e != hipSuccess || N == 0) return e;
-    k_run_bounds<G><<<grid_for(N, kB, 16384), kB, 0, st>>>(g, N, first, last);
+    k_run_bounds<G><<<grid_for((N + kBoundItems - 1) / kBoundItems, kB, 16384), kB, 0, st>>>(g, N, first, last);
     return hipGetLastError();
 }
 

@@ -158,6 +158,48 @@ def test_edge_cases(ctx):
         check(ctx, n, s, d, label)
 
 
+@pytest.mark.parametrize("pairs", [16383, 16384, 16385, 32769])
+def test_radix_tile_edges(ctx, pairs):
+    """Pair counts at and around the sort's 16384-key tile, so that the last tile is full,
+    one key long, or one key short."""
+    n = 3000
+    s, d = synth.er(n, pairs, seed=pairs)
+    check(ctx, n, s, d, f"ER pairs at a tile edge ({pairs})", offset_bytes=4)
+
+
+def test_ids_at_power_of_two(ctx):
+    """Vertex ids that need one more key bit than the rest of the graph: n = 2^16 + 1, with
+    triangles through the ids 2^16 - 1 and 2^16."""
+    n = (1 << 16) + 1
+    top, nxt = n - 1, n - 2
+    pairs = [(0, top), (top, nxt), (nxt, 0), (1, top), (1, nxt), (2, 3), (3, top), (2, top)]
+    pairs += [(i, i + 1) for i in range(4, 200)] + [(i, i + 2) for i in range(4, 200, 3)]
+    s, d = arr(pairs)
+    check(ctx, n, s, d, "ids 2^16 - 1 and 2^16", offset_bytes=8)
+
+
+def test_heavy_duplicates(ctx):
+    """Every undirected pair given ten times, in both directions and shuffled, plus loops."""
+    n, s, d = synth.rmat_scale(11, 8, seed=5)
+    rng = np.random.default_rng(3)
+    s10 = np.concatenate([s, d] * 5 + [np.arange(0, n, 7, dtype=np.int32)])
+    d10 = np.concatenate([d, s] * 5 + [np.arange(0, n, 7, dtype=np.int32)])
+    p = rng.permutation(len(s10))
+    check(ctx, n, s10[p].astype(np.int32), d10[p].astype(np.int32), "pairs x10, both ways, loops")
+
+
+def test_hub_over_random_graph(ctx):
+    """One vertex joined to all others over an ER graph: the hub ranks last (no out-list, every
+    vertex's in-edge), and every triangle through it is closed at its middle vertex."""
+    n = 5000
+    s, d = synth.er(n, 40000, seed=8)
+    hub = np.full(n - 1, 1234, dtype=np.int32)
+    others = np.array([v for v in range(n) if v != 1234], dtype=np.int32)
+    for ob in (4, 8):
+        check(ctx, n, np.concatenate([s, hub]), np.concatenate([d, others]), f"hub + ER (offsets {ob})",
+              offset_bytes=ob)
+
+
 def clique(n):
     a = np.array(list(itertools.combinations(range(n), 2)), dtype=np.int32)
     return a[:, 0].copy(), a[:, 1].copy()
