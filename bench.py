@@ -3,7 +3,7 @@
 One step = the whole path over one graph whose raw pairs are already in HBM:
 build (loop removal, sort, dedup, degrees, rank, orientation, reverse lists,
 work bins) + count (intersection + scatter) + LCC epilogue, then free.
-Prints one JSON line (see the design doc for the roofline accounting).
+Prints one JSON line with the roofline of the count kernel and the oracle's CPU rate.
 
     python bench.py [--steps K] [--warmup W] [--workload rmat_s23_ef16]
 """
@@ -53,7 +53,7 @@ def count_bytes(info) -> int:
             + (4 * w + 4) * int(info.active_vertices) + 8 * int(info.n))
 
 
-def survey_bytes(info) -> int:
+def full_list_bytes(info) -> int:
     """The whole-list streaming figure 4 W + (4 + 2w) m + (2w + 16) n, W = sum over oriented
     edges (u -> v) of |N+(v)|: bytes a push-style merge would read (reported for comparison)."""
     w = int(info.offset_bytes)
@@ -344,8 +344,8 @@ def main():
                     help="after timing, copy 1 GiB with an elementwise kernel 3 times (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(the path is single-GPU; see DESIGN.md for how it would shard)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the path runs on a "
+              f"single GPU (the graph, its count and its LCC live in one GPU's HBM)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -408,7 +408,7 @@ def main():
                      "kernel": "k_count (intersection + scatter)", "alg_bytes_per_launch": alg,
                      "avg_launch_ms": count_ms},
         "run_only_teps": m / (run_ms * 1e-3),
-        "survey_alg_frac": survey_bytes(info) / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "full_list_alg_frac": full_list_bytes(info) / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
         "run_resident": run_res,
         "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
