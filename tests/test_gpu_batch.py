@@ -168,3 +168,36 @@ def test_batch_progress_per_graph(ctx):
         assert lccs[i].cpu().numpy().tobytes() == lcc.cpu().numpy().tobytes()
     for g in graphs:
         g.free()
+
+
+def test_batch_degenerate_and_repeated_graphs(ctx):
+    """Graphs with no work (one vertex, no edges, only loops), tiny ones with and without
+    triangles, and one graph object submitted twice in the same batch (read-only sharing),
+    over both offset widths: each output equals the oracle's."""
+    print("[gpu] batch of degenerate and repeated graphs", flush=True)
+    cases = [
+        (1, []),
+        (7, []),
+        (4, [(0, 0), (1, 1), (3, 3)]),
+        (3, [(0, 1), (1, 0), (1, 2), (2, 1), (0, 2), (0, 2), (2, 2)]),
+        (60, [(0, i) for i in range(1, 60)]),
+        (40, list(itertools.combinations(range(40), 2))),
+    ]
+    raw = []
+    for n, pairs in cases:
+        a = np.array(pairs, dtype=np.int32).reshape(-1, 2)
+        raw.append((n, a[:, 0].copy(), a[:, 1].copy()))
+    raw.append(synth.rmat_scale(9, 16, seed=21))
+    graphs = [build(ctx, n, s, d, 4 if i % 2 == 0 else 8) for i, (n, s, d) in enumerate(raw)]
+    entries = graphs + [graphs[-1], graphs[3]]
+    expect = raw + [raw[-1], raw[3]]
+    tris, lccs = outputs(entries)
+    tk = ctx.batch_submit(entries, tris, lccs)
+    done, ndone = ctx.batch_poll(tk, block=True)
+    assert done and ndone == len(entries)
+    for (n, s, d), tri, lcc in zip(expect, tris, lccs):
+        t_ref, l_ref = oracle.tc_lcc(n, s, d)
+        np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
+        assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
+    for g in graphs:
+        g.free()
