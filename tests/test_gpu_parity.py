@@ -200,6 +200,24 @@ def test_hub_over_random_graph(ctx):
               offset_bytes=ob)
 
 
+@pytest.mark.parametrize("k", [100, 200])
+def test_wide_ids_packed_and_payload_in_edges(ctx, k):
+    """n just above 2^24 (25-bit ids), so the in-edge sort key takes four digit passes and leaves
+    32 bits under it for u and the row position.  A K_k at the top ids sets the largest
+    out-list: k = 100 (positions in 7 bits) still packs u and the position into the word, k = 200
+    (8 bits) does not, and the builder falls back to the edge index and a payload array.  Sparse
+    uniform pairs over the whole id range and a few links into the clique come on top."""
+    n = (1 << 24) + 3
+    top = np.arange(n - k, n, dtype=np.int32)
+    iu, ju = np.triu_indices(k, 1)
+    s0, d0 = synth.er(n, 20000, seed=k)
+    links_s = np.arange(0, 5000, 50, dtype=np.int32)
+    links_d = top[(links_s // 50) % k]
+    s = np.concatenate([top[iu], s0, links_s])
+    d = np.concatenate([top[ju], d0, links_d])
+    check(ctx, n, s.astype(np.int32), d.astype(np.int32), f"25-bit ids with K{k} at the top", offset_bytes=8)
+
+
 def clique(n):
     a = np.array(list(itertools.combinations(range(n), 2)), dtype=np.int32)
     return a[:, 0].copy(), a[:, 1].copy()
