@@ -221,7 +221,7 @@ typedef struct {
                                  when there are plenty (1..64; 0 = 8) */
     int32_t batch_heavy_bits; /* batched launch: vertices with >= 2^(bits-1) probes get a block
                                  (1..40; 0 = 15) */
-    int32_t row_sort_max;     /* builder: rows of N+ up to this long are sorted in LDS after a
+    int32_t row_sort_max;     /* builder: rows of N+ up to this long are sorted in registers after a
                                  sort by source rank (1..4096; 0 = 4096); if a longer row exists,
                                  the oriented edges get a full radix sort instead */
     int32_t reserved[4];      /* must be 0 */
