@@ -237,7 +237,30 @@ struct I32In {
 // ---- rows of the oriented CSR: after the sort by source rank, each row's entries are in
 // the order the relabel wrote them; these kernels sort every row by target rank in place.
 
-constexpr int kRowSortMax = 4096;  // longest row sorted in LDS (one wave, 16 KiB)
+constexpr int kRowSortMax = 4096;  // longest row sorted in registers (one wave, 64 entries per lane)
+
+// x as held by lane l ^ J.  J = 1, 2 are quad permutes and J = 8 a rotation of each 16-lane row
+// (DPP: plain VALU, no LDS); J = 4, 16 a swizzle within 32 lanes; J = 32 a permute by address.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x) {
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+    else if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);
+    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (J << 10) | 0x1F);
+    else return (uint32_t)__shfl_xor((int)x, J, kWave);
+}
+
+// The same for a j known once the caller's loop is unrolled.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x, int j) {
+    switch (j) {
+        case 1: return xor_lane<1>(x);
+        case 2: return xor_lane<2>(x);
+        case 4: return xor_lane<4>(x);
+        case 8: return xor_lane<8>(x);
+        case 16: return xor_lane<16>(x);
+        default: return xor_lane<32>(x);
+    }
+}
 
 // Ascending bitonic sort of one value per lane within each group of G lanes (G a power of two
 // up to 64): the usual network, with every group's last merge ascending.
@@ -248,7 +271,7 @@ __device__ __forceinline__ uint32_t group_bitonic_sort(uint32_t x) {
     for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t y = (uint32_t)__shfl_xor((int)x, j, kWave);
+            const uint32_t y = xor_lane(x, j);
             // within an ascending run of k lanes the lower lane of a pair keeps the smaller value
             const bool up = (k == G) || ((lane & k) == 0);
             const bool keep_min = up == ((lane & j) == 0);
@@ -339,9 +362,21 @@ __device__ __forceinline__ void reg_step(uint32_t (&v)[E], int k) {
     }
 }
 
+// Steps between lanes J apart (J < 64) of stage k.
+template <int E, int J>
+__device__ __forceinline__ void lane_step(uint32_t (&v)[E], int k) {
+    const int lane = lane_id();
+    const bool lower = (lane & J) == 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t y = xor_lane<J>(v[e]);
+        const bool up = (((e << 6) | lane) & k) == 0;
+        v[e] = (up == lower) ? min(v[e], y) : max(v[e], y);
+    }
+}
+
 template <int E>
 __device__ void reg_bitonic(uint32_t (&v)[E]) {
-    const int lane = lane_id();
 #pragma unroll 1
     for (int k = 2; k <= kWave * E; k <<= 1) {
 #pragma unroll 1
@@ -355,16 +390,13 @@ __device__ void reg_bitonic(uint32_t (&v)[E]) {
                 default: if constexpr (E > 32) reg_step<E, 32>(v, k); break;
             }
         }
-#pragma unroll 1
-        for (int j = min(k >> 1, kWave / 2); j > 0; j >>= 1) {
-            const bool lower = (lane & j) == 0;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const uint32_t y = (uint32_t)__shfl_xor((int)v[e], j, kWave);
-                const bool up = (((e << 6) | lane) & k) == 0;
-                v[e] = (up == lower) ? min(v[e], y) : max(v[e], y);
-            }
-        }
+        // then the steps between lanes, j = min(k / 2, 32) down to 1
+        if (k >= 64) lane_step<E, 32>(v, k);
+        if (k >= 32) lane_step<E, 16>(v, k);
+        if (k >= 16) lane_step<E, 8>(v, k);
+        if (k >= 8) lane_step<E, 4>(v, k);
+        if (k >= 4) lane_step<E, 2>(v, k);
+        lane_step<E, 1>(v, k);
     }
 }
 
