@@ -251,11 +251,15 @@ class Context:
 
     def batch_submit(self, graphs, tris, lccs=None) -> int:
         count = len(graphs)
-        gh = (ctypes.c_void_p * count)(*[g.handle for g in graphs])
-        th = (ctypes.c_void_p * count)(*[t.data_ptr() for t in tris])
-        lh = (ctypes.c_void_p * count)(*[(l.data_ptr() if l is not None else 0) for l in (lccs or [None] * count)])
+        # pointer arrays built by numpy from the handles and data pointers (a ctypes array built
+        # from a list of Python ints costs about twice as much for thousands of graphs)
+        gh = np.fromiter(((g.handle.value or 0) if g.handle else 0 for g in graphs), dtype=np.uint64, count=count)
+        th = np.fromiter((t.data_ptr() for t in tris), dtype=np.uint64, count=count)
+        lh = np.fromiter(((l.data_ptr() if l is not None else 0) for l in (lccs or [None] * count)),
+                         dtype=np.uint64, count=count)
         tk = ctypes.c_uint64()
-        _check(lib().tc_lcc_batch_submit(self.handle, count, gh, th, lh, ctypes.byref(tk)), "tc_lcc_batch_submit")
+        _check(lib().tc_lcc_batch_submit(self.handle, count, gh.ctypes.data, th.ctypes.data, lh.ctypes.data,
+                                         ctypes.byref(tk)), "tc_lcc_batch_submit")
         return int(tk.value)
 
     def batch_poll(self, ticket: int, block: bool = False):
