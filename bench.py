@@ -126,12 +126,17 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
     dev = torch.device("cuda", 0)
     graphs, tris, lccs = [], [], []
     m_total = 0
+    wedges = 0
+    alg_bytes = 0
     log_fn(f"[bench] building {len(specs)} batch graphs")
     for spec in specs:
         n, s, d = synth.make(spec)
         g = ctx.build_csr(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev), offset_bytes=4)
         graphs.append(g)
-        m_total += int(g.info().m)
+        info = g.info()
+        m_total += int(info.m)
+        wedges += int(info.wedges)
+        alg_bytes += count_bytes(info)
         tris.append(torch.empty(n, dtype=torch.int64, device=dev))
         lccs.append(torch.empty(n, dtype=torch.float64, device=dev))
     loop_tris = [torch.empty_like(t) for t in tris]
@@ -177,7 +182,7 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
     tt = float(np.median(t_tuned))
     return {"workload": "4096 graphs, n log-uniform in [64, 16384], half uniform (avg degree 8-32), "
                         "half R-MAT (EF 8-16), int32 offsets",
-            "graphs": len(specs), "m_total": m_total,
+            "graphs": len(specs), "m_total": m_total, "wedges": wedges, "alg_bytes": alg_bytes,
             "per_graph_ms": tl * 1e3, "batched_ms": tb * 1e3, "speedup": tl / tb,
             "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same),
             "autotuned": {"batch_grab": tuned.batch_grab, "batch_heavy_bits": tuned.batch_heavy_bits,
