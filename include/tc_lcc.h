@@ -218,7 +218,7 @@ typedef struct {
     int32_t merge_ratio_x100; /* PROBE_MERGE: Eq. 3's right side is scaled by this / 100
                                  (0 = 100, the rule as printed; 0..100000) */
     int32_t batch_grab;       /* batched launch: light vertices a wave takes per queue access
-                                 when there are plenty (1..64; 0 = 8) */
+                                 when there are plenty (1..64; 0 = 16) */
     int32_t batch_heavy_bits; /* batched launch: vertices with >= 2^(bits-1) probes get a block
                                  (1..40; 0 = 15) */
     int32_t row_sort_max;     /* builder: rows of N+ up to this long are sorted in registers after a

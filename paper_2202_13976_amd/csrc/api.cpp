@@ -27,7 +27,7 @@ tc_lcc_tuning default_tuning() {
     t.wave_outdeg_max = 0;
     t.block_threads = 256;
     t.merge_ratio_x100 = 0;
-    t.batch_grab = 8;
+    t.batch_grab = 16;
     t.batch_heavy_bits = kBigWorkBits;
     return t;
 }

@@ -499,7 +499,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), (size_t)count, std::max<size_t>(scratch, 1));
     if (st != TC_LCC_OK) return st;
 
-    int grab = 8, heavy_bits = kBigWorkBits;
+    int grab = 16, heavy_bits = kBigWorkBits;
     {
         std::lock_guard<std::mutex> tl(ctx->mu);
         if (ctx->tuning.batch_grab > 0) grab = ctx->tuning.batch_grab;
