@@ -141,16 +141,32 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
     for (int64_t item = lo + ((grid - 1 - blockIdx.x) * (int64_t)(kBatchThreads / kWave) + w) * grab;;) {
         if (item >= hi) break;
         const int64_t end = min(item + (int64_t)grab, hi);
-        int g = __builtin_amdgcn_readfirstlane(batch_graph_of<false>(gs, g_lo, g_hi, item));
-        for (; item < end; ++item) {
-            while (item >= gs[g].light_base + gs[g].light) ++g;  // graphs without light vertices
-            const BatchGraph& G = gs[g];
+        // the grab's vertices with their graphs and list bounds, lane q holding item + q, all
+        // loaded at once (a grab has at most 64 vertices)
+        int gq = __builtin_amdgcn_readfirstlane(batch_graph_of<false>(gs, g_lo, g_hi, item));
+        int32_t hv = 0;
+        OffT hb0 = 0, hb1 = 0, hi0 = 0, hi1 = 0;
+        if (item + lane < end) {
+            const int64_t it = item + lane;
+            while (it >= gs[gq].light_base + gs[gq].light) ++gq;  // graphs without light vertices
+            const BatchGraph& GL = gs[gq];
+            const OffT* oo = (const OffT*)GL.out_off;
+            const OffT* io = (const OffT*)GL.in_off;
+            hv = GL.vlist[GL.heavy + (it - GL.light_base)];
+            hb0 = oo[hv];
+            hb1 = oo[hv + 1];
+            hi0 = io[hv];
+            hi1 = io[hv + 1];
+        }
+        for (int q = 0; item < end; ++item, ++q) {
+            const BatchGraph& G = gs[__builtin_amdgcn_readlane(gq, q)];
             const CountArgs<OffT> a = batch_args<OffT>(G);
-            const int32_t v = G.vlist[G.heavy + (item - G.light_base)];
+            const VertexHead<OffT> hd{__builtin_amdgcn_readlane(hv, q), lane_value(hb0, q), lane_value(hb1, q),
+                                      lane_value(hi0, q), lane_value(hi1, q)};
             unsigned long long local = 0;
-            process_vertex<OffT, TC_LCC_PROBE_AUTO, 1>(a, v, region, rb, lane, 0, local);
+            process_vertex<OffT, TC_LCC_PROBE_AUTO, 1>(a, hd, region, rb, lane, 0, local);
             const unsigned long long ws = wave_sum(local);
-            if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
+            if (lane == 0 && ws) atomicAdd(&G.t[hd.v], ws);
         }
         if (waves * grab >= hi - lo) break;
         unsigned int q = 0;
@@ -502,7 +518,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     int grab = 16, heavy_bits = kBigWorkBits;
     {
         std::lock_guard<std::mutex> tl(ctx->mu);
-        if (ctx->tuning.batch_grab > 0) grab = ctx->tuning.batch_grab;
+        if (ctx->tuning.batch_grab > 0) grab = std::min(ctx->tuning.batch_grab, kWave);  // a lane per vertex of a grab
         if (ctx->tuning.batch_heavy_bits > 0) heavy_bits = ctx->tuning.batch_heavy_bits;
     }
     const uint32_t seq = e->next_seq++;
