@@ -83,17 +83,25 @@ __device__ __forceinline__ CountArgs<OffT> batch_args(const BatchGraph& G) {
     return a;
 }
 
-// Last graph g in [g_lo, g_hi) whose items start at or before `item` (base selects the
-// heavy or the light numbering).
+// Last graph g in [g_lo, g_hi) whose items start at or before `item` (HEAVY selects the heavy
+// or the light numbering), found by the whole wave (all lanes active, `item` wave-uniform):
+// each round the lanes test 64 evenly spaced graphs of the remaining range at once, so 4096
+// graphs take two rounds of one load each instead of twelve dependent loads.  The bases grow
+// with g and the first graph's base is at most `item`, so the lanes that pass form a prefix.
 template <bool HEAVY>
-__device__ __forceinline__ int batch_graph_of(const BatchGraph* __restrict__ gs, int g_lo, int g_hi, int64_t item) {
-    int ga = g_lo, gb = g_hi - 1;
-    while (ga < gb) {
-        const int mid = (ga + gb + 1) >> 1;
-        if ((HEAVY ? gs[mid].heavy_base : gs[mid].light_base) <= item) ga = mid;
-        else gb = mid - 1;
+__device__ __forceinline__ int batch_graph_of_wave(const BatchGraph* __restrict__ gs, int g_lo, int g_hi,
+                                                   int64_t item) {
+    const int lane = lane_id();
+    int lo = g_lo, hi = g_hi;  // the answer lies in [lo, hi)
+    while (hi - lo > 1) {
+        const int step = (hi - lo + kWave - 1) / kWave;
+        const int gi = lo + lane * step;
+        const bool pass = gi < hi && (HEAVY ? gs[gi].heavy_base : gs[gi].light_base) <= item;
+        const int k = (int)__popcll(__builtin_amdgcn_ballot_w64(pass));
+        lo += (k - 1) * step;
+        hi = min(hi, lo + step);
     }
-    return ga;
+    return lo;
 }
 
 // Two phases, as in the single-graph kernel: the heavy vertices of all graphs (those with at
@@ -115,7 +123,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
     const int64_t hlo = which ? h->heavy4 : 0, hhi = which ? h->heavy : h->heavy4;
     for (int64_t item = hlo + blockIdx.x;;) {
         if (item >= hhi) break;
-        int g = __builtin_amdgcn_readfirstlane(batch_graph_of<true>(gs, g_lo, g_hi, item));
+        int g = __builtin_amdgcn_readfirstlane(batch_graph_of_wave<true>(gs, g_lo, g_hi, item));
         while (item >= gs[g].heavy_base + gs[g].heavy) ++g;  // graphs without heavy vertices
         const BatchGraph& G = gs[g];
         const CountArgs<OffT> a = batch_args<OffT>(G);
@@ -143,7 +151,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
         const int64_t end = min(item + (int64_t)grab, hi);
         // the grab's vertices with their graphs and list bounds, lane q holding item + q, all
         // loaded at once (a grab has at most 64 vertices)
-        int gq = __builtin_amdgcn_readfirstlane(batch_graph_of<false>(gs, g_lo, g_hi, item));
+        int gq = __builtin_amdgcn_readfirstlane(batch_graph_of_wave<false>(gs, g_lo, g_hi, item));
         int32_t hv = 0;
         OffT hb0 = 0, hb1 = 0, hi0 = 0, hi1 = 0;
         if (item + lane < end) {
