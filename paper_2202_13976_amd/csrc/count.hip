@@ -52,13 +52,15 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs<OffT> a) {
     const int64_t grid = gridDim.x;
     for (int64_t it = blockIdx.x;;) {
         if (it >= a.n_block) break;
+        // the next item is taken from the queue before this one is worked on, so the atomic's
+        // round trip overlaps the work (every thread has read the previous one by now)
+        if (threadIdx.x == 0 && grid < a.n_block) s_item = grid + (int64_t)atomicAdd(&a.ctr[0], 1u);
         const int32_t v = a.vlist[it];
         unsigned long long local = 0;
         process_vertex<OffT, PROBE, kWavesPerBlock>(a, v, lds, block_bytes, threadIdx.x, w, local);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&a.t[v], ws);
         if (grid >= a.n_block) break;
-        if (threadIdx.x == 0) s_item = grid + (int64_t)atomicAdd(&a.ctr[0], 1u);
         __syncthreads();
         it = s_item;
         __syncthreads();
