@@ -294,7 +294,8 @@ def test_invalid_inputs(ctx):
 @pytest.mark.parametrize("row_sort_max", [0, 1])
 def test_builder_structure(ctx, row_sort_max):
     """The exported CSR: degrees, rank order by (degree, id), orientation and sorted lists,
-    and the number of kept in-edges.  row_sort_max 0 sorts rows in LDS after the sort by
+    and the schedule's counts (kept in-edges, probes, active vertices, staged entries) that
+    the roofline accounting uses.  row_sort_max 0 sorts rows in registers after the sort by
     source (rows of 2..64 and of 65..4096 entries take different kernels); 1 sends the
     oriented edges through the full radix sort instead."""
     n, s, d = synth.rmat_scale(14, 16, seed=3)
@@ -332,3 +333,8 @@ def test_builder_structure(ctx, row_sort_max):
     assert info.kept_in_edges == int(np.count_nonzero(kept))
     # probes (oriented wedges that can close): the sum of the kept in-edges' tail lengths
     assert info.wedges == int(tail[kept].sum())
+    # active vertices: those with probes (a kept in-edge); staged entries: their |N+(v)|
+    work = np.bincount(adj[kept], weights=tail[kept], minlength=n)
+    active = work > 0
+    assert info.active_vertices == int(np.count_nonzero(active))
+    assert info.staged_entries == int(dplus[active].sum())
