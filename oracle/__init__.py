@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 benchmark's CPU-baseline leg, never by the GPU library, and it shares no code
 with it.  Every routine follows its definition in Strausz et al. (Sec. II-C,
-Eq. 2, Alg. 1-3); see oracle.c for the readings of the paper it takes.
+Eq. 1, Eq. 2, Alg. 1-3, and the per-edge counts of Sec. V-B); see oracle.c for the
+readings of the paper it takes.
 """
 from __future__ import annotations
 
@@ -59,6 +60,16 @@ def _load():
         lib.oracle_lcc_one.restype = ctypes.c_double
         lib.oracle_lcc.argtypes = [i64, vp, vp, vp]
         lib.oracle_lcc.restype = None
+        lib.oracle_edge_counts.argtypes = [i64, vp, vp, vp, vp, vp]
+        lib.oracle_edge_counts.restype = i64
+        lib.oracle_csr_directed.argtypes = [i64, i64, vp, vp, vp, vp]
+        lib.oracle_csr_directed.restype = i64
+        lib.oracle_tc_directed.argtypes = [i64, vp, vp, vp]
+        lib.oracle_tc_directed.restype = None
+        lib.oracle_lcc_directed_one.argtypes = [u64, i64]
+        lib.oracle_lcc_directed_one.restype = ctypes.c_double
+        lib.oracle_lcc_directed.argtypes = [i64, vp, vp, vp]
+        lib.oracle_lcc_directed.restype = None
         _lib = lib
     return _lib
 
@@ -158,6 +169,55 @@ def lcc(g: CSR, t: np.ndarray) -> np.ndarray:
     out = np.empty(g.n, dtype=np.float64)
     _load().oracle_lcc(g.n, _p(g.off), _p(t), _p(out))
     return out
+
+
+def edge_counts(g: CSR):
+    """Per-edge triangle counts (Sec. V-B, C = A A o A): (eu, ev, c) over the edges {eu < ev}
+    in upper-triangle CSR order, c = |adj(eu) ∩ adj(ev)|."""
+    m = g.m
+    eu = np.empty(max(m, 1), dtype=np.int32)
+    ev = np.empty(max(m, 1), dtype=np.int32)
+    c = np.empty(max(m, 1), dtype=np.uint64)
+    k = _load().oracle_edge_counts(g.n, _p(g.off), _p(g.adj), _p(eu), _p(ev), _p(c))
+    assert k == m
+    return eu[:m], ev[:m], c[:m]
+
+
+def csr_directed(n: int, src, dst) -> CSR:
+    """Out-list CSR of the directed graph behind the pairs (loops and repeats removed)."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    off = np.empty(n + 1, dtype=np.int64)
+    adj = np.empty(max(len(src), 1), dtype=np.int32)
+    nnz = _load().oracle_csr_directed(n, len(src), _p(src), _p(dst), _p(off), _p(adj))
+    if nnz < 0:
+        raise ValueError("endpoint outside [0, n)")
+    return CSR(n, off, adj[:nnz].copy())
+
+
+def tc_directed(g: CSR) -> np.ndarray:
+    """Numerator of Eq. 1 per vertex: edges e_jk with v_j, v_k out-neighbours of v_i."""
+    num = np.empty(g.n, dtype=np.uint64)
+    _load().oracle_tc_directed(g.n, _p(g.off), _p(g.adj), _p(num))
+    return num
+
+
+def lcc_directed_one(num: int, dout: int) -> float:
+    return float(_load().oracle_lcc_directed_one(num, dout))
+
+
+def lcc_directed(g: CSR, num: np.ndarray) -> np.ndarray:
+    num = np.ascontiguousarray(num, dtype=np.uint64)
+    out = np.empty(g.n, dtype=np.float64)
+    _load().oracle_lcc_directed(g.n, _p(g.off), _p(num), _p(out))
+    return out
+
+
+def tc_lcc_directed(n: int, src, dst):
+    """Per-vertex (numerator of Eq. 1, directed LCC of Eq. 1) of the raw directed pairs."""
+    g = csr_directed(n, src, dst)
+    num = tc_directed(g)
+    return num, lcc_directed(g, num)
 
 
 def tc_lcc(n: int, src, dst, method: str = "forward"):

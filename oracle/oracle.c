@@ -24,6 +24,12 @@
  *     listing is not followed line by line.
  *   - Eq. 3 picks SSI when |B|/|A| <= log2|B| - 1 (ties go to SSI).
  *
+ * Also here, for the two extensions of the same method:
+ *   c(e)   = triangles containing edge e = {i, j}: |adj(i) ∩ adj(j)|, the entry
+ *            c_ij of C = A A o A (Sec. V-B), one per undirected edge;
+ *   directed graphs (Eq. 1): adj(v_i) = out-neighbours, numerator = edges e_jk
+ *            with v_j, v_k in adj(v_i), denominator deg+(v_i) (deg+(v_i) - 1).
+ *
  * Pins: the tests check every function here against brute force written in
  * the test itself, closed forms, dense and sparse linear algebra (the algebraic
  * form of Sec. V-B), networkx, and exact rational arithmetic for the LCC bits.
@@ -293,4 +299,98 @@ double oracle_lcc_one(uint64_t t, int64_t d) {
 
 void oracle_lcc(int64_t n, const int64_t* off, const uint64_t* t, double* lcc) {
     for (int64_t v = 0; v < n; ++v) lcc[v] = oracle_lcc_one(t[v], off[v + 1] - off[v]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Per-edge triangle counts (Sec. V-B: C = A A o A)                          */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Entry c_ij of C = A A o A is the number of triangles that contain the edge
+ * e_ij: the common neighbours of i and j, |adj(i) ∩ adj(j)| (Alg. 2).  One
+ * output per undirected edge {i, j}, i < j, in the order of the CSR's upper
+ * triangle (i ascending, then j ascending).  eu, ev and c need m = off[n] / 2
+ * entries.  Returns the number of edges written.
+ */
+int64_t oracle_edge_counts(int64_t n, const int64_t* off, const int32_t* adj, int32_t* eu, int32_t* ev,
+                           uint64_t* c) {
+    int64_t e = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+            int32_t j = adj[p];
+            if (j <= i) continue;
+            eu[e] = (int32_t)i;
+            ev[e] = j;
+            c[e] = oracle_ssi(adj + off[i], off[i + 1] - off[i], adj + off[j], off[j + 1] - off[j]);
+            ++e;
+        }
+    return e;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Directed graphs: Eq. 1                                                    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * CSR of the directed graph behind the raw pairs (Sec. II-A: e_ij is the edge
+ * from v_i to v_j, adj(v_i) its out-neighbours): self-loops dropped, repeats of
+ * the same ordered pair removed, each out-list sorted.  off has n + 1 entries,
+ * adj room for m_in.  Returns the number of edges, or -1 for an endpoint
+ * outside [0, n).
+ */
+int64_t oracle_csr_directed(int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst, int64_t* off,
+                            int32_t* adj) {
+    for (int64_t e = 0; e < m_in; ++e)
+        if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return -1;
+    int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < m_in; ++e)
+        if (src[e] != dst[e]) cnt[src[e] + 1]++;
+    for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t e = 0; e < m_in; ++e)
+        if (src[e] != dst[e]) adj[fill[src[e]]++] = dst[e];
+    free(fill);
+    int64_t out = 0;
+    off[0] = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t b = cnt[v], e = cnt[v + 1];
+        qsort(adj + b, (size_t)(e - b), sizeof(int32_t), cmp_i32);
+        int64_t start = out;
+        for (int64_t i = b; i < e; ++i)
+            if (out == start || adj[out - 1] != adj[i]) adj[out++] = adj[i];
+        off[v + 1] = out;
+    }
+    free(cnt);
+    return out;
+}
+
+/*
+ * Numerator of Eq. 1 for every vertex i: the edges e_jk with v_j, v_k in
+ * adj(v_i).  Edge-centric as in Sec. II-C: for every e_ij, the out-neighbours of
+ * j that are also out-neighbours of i, |adj(i) ∩ adj(j)| (Alg. 2).  There is no
+ * upper-triangle offset here: e_jk and e_kj are different edges of a directed
+ * graph and each one present counts.
+ */
+void oracle_tc_directed(int64_t n, const int64_t* off, const int32_t* adj, uint64_t* num) {
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t s = 0;
+        for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+            int32_t j = adj[p];
+            s += oracle_ssi(adj + off[i], off[i + 1] - off[i], adj + off[j], off[j + 1] - off[j]);
+        }
+        num[i] = s;
+    }
+}
+
+/* Eq. 1: C(i) = num(i) / (deg+(i) (deg+(i) - 1)), both integers exact in 64 bits and one
+ * IEEE binary64 division (round to nearest even); deg+ < 2 gives 0.0. */
+double oracle_lcc_directed_one(uint64_t num, int64_t dout) {
+    if (dout < 2) return 0.0;
+    uint64_t den = (uint64_t)dout * (uint64_t)(dout - 1);
+    return (double)num / (double)den;
+}
+
+void oracle_lcc_directed(int64_t n, const int64_t* off, const uint64_t* num, double* lcc) {
+    for (int64_t v = 0; v < n; ++v) lcc[v] = oracle_lcc_directed_one(num[v], off[v + 1] - off[v]);
 }

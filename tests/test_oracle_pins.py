@@ -168,6 +168,22 @@ def test_windmill(k):
     assert np.all(lcc[1:] == 1.0)
 
 
+@pytest.mark.parametrize("k,size", [(3, 1), (3, 4), (5, 3), (7, 6)])
+def test_complete_multipartite(k, size):
+    """k parts of `size` vertices, every pair in different parts joined: each vertex has
+    d = (k-1) size and t = C(d, 2) - (k-1) C(size, 2) (neighbour pairs inside one other part
+    are not joined); LCC = 2 t / (d (d - 1)).  Dense, yet most neighbour pairs of the same
+    part miss, unlike K_n."""
+    n = k * size
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n) if a // size != b // size]
+    t, lcc, g = run(n, pairs)
+    d = (k - 1) * size
+    want = math.comb(d, 2) - (k - 1) * math.comb(size, 2)
+    assert np.all(g.deg == d)
+    assert np.all(t == want)
+    assert np.all(lcc == (float(Fraction(2 * want, d * (d - 1))) if d >= 2 else 0.0))
+
+
 def test_empty_and_isolated():
     t, lcc, g = run(5, [])
     assert t.tolist() == [0] * 5 and lcc.tolist() == [0.0] * 5 and g.m == 0
@@ -322,3 +338,137 @@ def test_eq3_rule():
     assert not oracle.eq3_prefers_ssi(100, 1000) # 10 > 8.97
     assert not oracle.eq3_prefers_ssi(10, 1000)  # 100 > 8.97
     assert oracle.eq3_prefers_ssi(8, 4) == oracle.eq3_prefers_ssi(4, 8)
+
+
+# --------------------------------------------------------------------------- per-edge counts (Sec. V-B)
+
+def py_edge_counts(n, pairs):
+    """Common neighbours of every edge {i < j}, by Python sets, in (i, j) order."""
+    adj = [set() for _ in range(n)]
+    for u, v in pairs:
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    out = []
+    for i in range(n):
+        for j in sorted(adj[i]):
+            if j > i:
+                out.append((i, j, len(adj[i] & adj[j])))
+    return out
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 30).flatmap(lambda n: st.tuples(
+    st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=150))))
+def test_edge_counts_brute_force(case):
+    n, pairs = case
+    src = np.array([p[0] for p in pairs], dtype=np.int32)
+    dst = np.array([p[1] for p in pairs], dtype=np.int32)
+    g = oracle.csr(n, src, dst)
+    eu, ev, c = oracle.edge_counts(g)
+    want = py_edge_counts(n, pairs)
+    assert list(zip(eu.tolist(), ev.tolist(), c.tolist())) == want
+
+
+def test_edge_counts_scipy_and_invariants():
+    """C = (A A) o A with scipy on R-MAT S13: the upper-triangle entries in CSR order; sum of
+    c over the edges = 3 T; sum over the edges at i = 2 t(i)."""
+    import scipy.sparse as sp
+    n, s, d = synth.rmat_scale(13, 16, seed=17)
+    g = oracle.csr(n, s, d)
+    eu, ev, c = oracle.edge_counts(g)
+    rows = np.repeat(np.arange(n), g.deg)
+    A = sp.csr_matrix((np.ones(len(g.adj), dtype=np.int64), (rows, g.adj)), shape=(n, n))
+    C = sp.triu((A @ A).multiply(A), k=1).tocsr()
+    C.sort_indices()
+    Ccoo = C.tocoo()
+    # scipy drops the explicit zeros of edges without triangles: compare on the edge list
+    dense_vals = dict(zip(zip(Ccoo.row.tolist(), Ccoo.col.tolist()), Ccoo.data.tolist()))
+    want = np.array([dense_vals.get((a, b), 0) for a, b in zip(eu.tolist(), ev.tolist())], dtype=np.uint64)
+    np.testing.assert_array_equal(c, want)
+    t = oracle.tc_forward(g)
+    assert int(c.sum()) == int(t.sum())  # sum over edges = 3 T = sum over vertices
+    per_vertex = np.bincount(eu, weights=c, minlength=n) + np.bincount(ev, weights=c, minlength=n)
+    np.testing.assert_array_equal(per_vertex.astype(np.uint64), 2 * t)
+
+
+@pytest.mark.parametrize("n", [3, 4, 9, 30])
+def test_edge_counts_complete_graph(n):
+    s, d = (x.astype(np.int32) for x in np.triu_indices(n, 1))
+    eu, ev, c = oracle.edge_counts(oracle.csr(n, s, d))
+    assert len(c) == n * (n - 1) // 2 and np.all(c == n - 2)
+
+
+# --------------------------------------------------------------------------- directed graphs (Eq. 1)
+
+def py_directed(n, pairs):
+    """Eq. 1 by enumeration: ordered pairs (j, k), j != k, with i -> j, i -> k and j -> k."""
+    out = [set() for _ in range(n)]
+    for u, v in pairs:
+        if u != v:
+            out[u].add(v)
+    num = [0] * n
+    for i in range(n):
+        for j in out[i]:
+            for k in out[i]:
+                if j != k and k in out[j]:
+                    num[i] += 1
+    dout = [len(o) for o in out]
+    lcc = [float(Fraction(num[i], dout[i] * (dout[i] - 1))) if dout[i] >= 2 else 0.0 for i in range(n)]
+    return np.array(num, dtype=np.uint64), np.array(lcc), np.array(dout)
+
+
+@settings(max_examples=80, deadline=None)
+@given(st.integers(1, 25).flatmap(lambda n: st.tuples(
+    st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=160))))
+def test_directed_brute_force(case):
+    n, pairs = case
+    src = np.array([p[0] for p in pairs], dtype=np.int32)
+    dst = np.array([p[1] for p in pairs], dtype=np.int32)
+    num_ref, lcc_ref, dout_ref = py_directed(n, pairs)
+    g = oracle.csr_directed(n, src, dst)
+    np.testing.assert_array_equal(g.deg, dout_ref)
+    num, lcc = oracle.tc_lcc_directed(n, src, dst)
+    np.testing.assert_array_equal(num, num_ref)
+    assert lcc.tobytes() == lcc_ref.tobytes()
+
+
+def test_directed_dense_algebraic():
+    """Numerator of Eq. 1 = rowsum((A A) o A) for the directed adjacency A (no halving):
+    (A A)_ik counts the paths i -> j -> k, o A keeps those with i -> k."""
+    rng = np.random.default_rng(5)
+    n = 400
+    A = (rng.random((n, n)) < 0.05).astype(np.float64)
+    np.fill_diagonal(A, 0.0)
+    src, dst = (x.astype(np.int32) for x in np.nonzero(A))
+    num, _ = oracle.tc_lcc_directed(n, src, dst)
+    np.testing.assert_array_equal(num, ((A @ A) * A).sum(axis=1).astype(np.uint64))
+
+
+@pytest.mark.parametrize("n", [3, 5, 12])
+def test_directed_closed_forms(n):
+    # complete digraph (both directions): num = d (d - 1), C = 1
+    pairs = [(a, b) for a in range(n) for b in range(n) if a != b]
+    src = np.array([p[0] for p in pairs], dtype=np.int32)
+    dst = np.array([p[1] for p in pairs], dtype=np.int32)
+    num, lcc = oracle.tc_lcc_directed(n, src, dst)
+    assert np.all(num == (n - 1) * (n - 2)) and np.all(lcc == 1.0)
+    # transitive tournament (a -> b iff a < b): out(i) = {i+1 .. n-1}, num = C(n-1-i, 2), C = 1/2
+    s, d = (x.astype(np.int32) for x in np.triu_indices(n, 1))
+    num, lcc = oracle.tc_lcc_directed(n, s, d)
+    dout = n - 1 - np.arange(n)
+    assert num.tolist() == [math.comb(int(k), 2) for k in dout]
+    assert np.all(lcc[dout >= 2] == 0.5) and np.all(lcc[dout < 2] == 0.0)
+    # directed cycle: one out-neighbour each, no numerator
+    cyc = np.arange(n, dtype=np.int32)
+    num, lcc = oracle.tc_lcc_directed(n, cyc, np.roll(cyc, -1))
+    assert np.all(num == 0) and np.all(lcc == 0.0)
+
+
+def test_directed_symmetric_input_is_undirected():
+    """Both directions of every edge: num = 2 t(v) and Eq. 1 gives Eq. 2's bits."""
+    n, s, d = synth.rmat_scale(11, 16, seed=9)
+    t, lcc_u = oracle.tc_lcc(n, s, d)
+    num, lcc_d = oracle.tc_lcc_directed(n, np.concatenate([s, d]), np.concatenate([d, s]))
+    np.testing.assert_array_equal(num, 2 * t)
+    assert lcc_d.tobytes() == lcc_u.tobytes()
