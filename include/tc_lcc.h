@@ -58,8 +58,15 @@ tc_lcc_status tc_lcc_ctx_create(int device, uint64_t hbm_budget_bytes, tc_lcc_ct
  * it must be freed first (BUSY otherwise). */
 tc_lcc_status tc_lcc_ctx_destroy(tc_lcc_ctx ctx);
 
-/* Device bytes the context currently holds (graphs + cached pool blocks). */
+/* Device bytes the context currently holds: in_use = blocks owned by graphs, batch slots and
+ * running builds; pooled = released blocks the context keeps for reuse. */
 tc_lcc_status tc_lcc_ctx_memory(tc_lcc_ctx ctx, uint64_t* in_use, uint64_t* pooled);
+
+/* Testing aid for the failure paths: the context's next `after` device allocations succeed
+ * and the one after them fails with OUT_OF_MEMORY, as if HBM were exhausted (after < 0 turns
+ * it off; it is off in a new context).  Every call that fails this way writes no output and
+ * leaves the context usable. */
+tc_lcc_status tc_lcc_debug_fail_alloc(tc_lcc_ctx ctx, int64_t after);
 
 /* ------------------------------------------------------------------ graphs */
 

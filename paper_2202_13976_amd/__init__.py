@@ -71,7 +71,7 @@ class RequestInfo(ctypes.Structure):
 
 _lib = None
 EXPORTS = [
-    "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_build_csr", "tc_lcc_graph_info",
+    "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_debug_fail_alloc", "tc_lcc_build_csr", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
     "tc_lcc_batch_progress", "tc_lcc_autotune", "tc_lcc_tuning_load",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
@@ -93,6 +93,7 @@ def lib():
     L.tc_lcc_ctx_create.argtypes = [i32, u64, ctypes.POINTER(vp)]
     L.tc_lcc_ctx_destroy.argtypes = [vp]
     L.tc_lcc_ctx_memory.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    L.tc_lcc_debug_fail_alloc.argtypes = [vp, i64]
     L.tc_lcc_build_csr.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
     L.tc_lcc_graph_info.argtypes = [vp, ctypes.POINTER(GraphStats)]
     L.tc_lcc_graph_export.argtypes = [vp, vp, vp, vp, vp]
@@ -248,6 +249,11 @@ class Context:
         a, b = ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().tc_lcc_ctx_memory(self.handle, ctypes.byref(a), ctypes.byref(b)), "tc_lcc_ctx_memory")
         return int(a.value), int(b.value)
+
+    def fail_alloc_after(self, after: int):
+        """Failure injection (tc_lcc_debug_fail_alloc): the next `after` device allocations
+        succeed, the one after fails; a negative value turns it off."""
+        _check(lib().tc_lcc_debug_fail_alloc(self.handle, after), "tc_lcc_debug_fail_alloc")
 
     def batch_submit(self, graphs, tris, lccs=None) -> int:
         count = len(graphs)

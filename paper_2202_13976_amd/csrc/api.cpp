@@ -45,9 +45,18 @@ size_t Pool::round(size_t bytes) {
     return (bytes + g - 1) / g * g;
 }
 
+void Pool::fail_after(int64_t after) {
+    std::lock_guard<std::mutex> lk(mu_);
+    fail_after_ = after;
+}
+
 tc_lcc_status Pool::alloc(size_t bytes, void** out) {
     const size_t sz = round(bytes);
     std::lock_guard<std::mutex> lk(mu_);
+    if (fail_after_ >= 0 && fail_after_-- == 0) {
+        set_error("device allocation of %zu bytes refused (failure injection)", sz);
+        return TC_LCC_OUT_OF_MEMORY;
+    }
     auto it = free_.find(sz);
     if (it != free_.end()) {
         void* p = it->second;
@@ -160,6 +169,11 @@ extern "C" tc_lcc_status tc_lcc_ctx_create(int device, uint64_t hbm_budget_bytes
     c->tuning = default_tuning();
     c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->lds_per_block = prop.sharedMemPerBlock;
+    const tc_lcc_status bs = batch_engine_create(c);
+    if (bs != TC_LCC_OK) {
+        delete c;
+        return bs;
+    }
     *out = c;
     return TC_LCC_OK;
 }
@@ -187,6 +201,15 @@ extern "C" tc_lcc_status tc_lcc_ctx_memory(tc_lcc_ctx ctx, uint64_t* in_use, uin
     }
     if (in_use) *in_use = ctx->pool->in_use();
     if (pooled) *pooled = ctx->pool->pooled();
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_debug_fail_alloc(tc_lcc_ctx ctx, int64_t after) {
+    if (!ctx) {
+        set_error("tc_lcc_debug_fail_alloc: null context");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    ctx->pool->fail_after(after);
     return TC_LCC_OK;
 }
 
@@ -362,7 +385,8 @@ extern "C" tc_lcc_status tc_lcc_graph_free(tc_lcc_graph g) {
 
 // ------------------------------------------------------------------ one graph
 
-tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu) {
+tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu,
+                             bool engine_locked) {
     tc_lcc_ctx ctx = g->ctx;
     TCL_HIP(hipSetDevice(ctx->device));
     tc_lcc_tuning tn;
@@ -372,13 +396,24 @@ tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStre
         tn = ctx->tuning;
         gen = ctx->tuning_gen;
     }
-    std::lock_guard<std::mutex> lk(g->mu);
+    std::unique_lock<std::mutex> el;
+    std::unique_lock<std::mutex> lk(g->mu);
+    if (g->d.sched_gen != gen && !engine_locked) {
+        // a schedule rebuild rewrites the vertex list that batches in flight read: take the
+        // engine's lock (before the graph's) so that no batch starts meanwhile, and wait for
+        // the batches that hold the graph
+        lk.unlock();
+        el = std::unique_lock<std::mutex>(batch_mutex(ctx));
+        lk.lock();
+    }
     TCL_HIP(hipStreamWaitEvent(st, g->last_use, 0));
     if (g->d.sched_gen != gen) {
-        tc_lcc_status s = build_schedule(g, tn, st);
+        tc_lcc_status s = batch_fence_graph(ctx, g, st);
+        if (s == TC_LCC_OK) s = build_schedule(g, tn, st);
         if (s != TC_LCC_OK) return s;
         g->d.sched_gen = gen;
     }
+    if (el.owns_lock()) el.unlock();
     mark(g->d, 6, st);
     tc_lcc_status s = launch_zero_counts(g, st);
     mark(g->d, 7, st);

@@ -280,79 +280,92 @@ struct Engine {
     std::map<uint64_t, int> completed;  // tickets finished before their poll: graphs done
 };
 
-Engine* engine(tc_lcc_ctx ctx) {
-    if (!ctx->batch) ctx->batch = new Engine();
-    return (Engine*)ctx->batch;
-}
+// created with the context (tc_lcc_ctx_create), so no two threads race to create it
+Engine* engine(tc_lcc_ctx ctx) { return (Engine*)ctx->batch; }
 
 void drop_execs(Slot& s) {
     for (auto& kv : s.execs) (void)hipGraphExecDestroy(kv.second);
     s.execs.clear();
 }
 
-// Device buffers of a free slot.  New counters are cleared here, on the slot's stream; after
-// that every batch leaves the counters it used at zero (the epilogue resets them).
+// Device buffers of a free slot (no device work uses its buffers).  Each replacement is
+// allocated before the buffer it replaces is released, so a failed allocation leaves the slot
+// as it was; every change of a buffer drops the captured launches that point at it.  New
+// counters are cleared here, on the slot's stream; after that every batch leaves the counters
+// it used at zero (the epilogue resets them).
 tc_lcc_status ensure_capacity(tc_lcc_ctx ctx, Slot& s, size_t graphs, size_t flags, size_t scratch) {
     Pool* pool = ctx->pool.get();
-    bool changed = false;
     if (flags > s.cap_done) {
         const size_t cap = std::max<size_t>(flags, 2 * s.cap_done);
-        if (s.h_done) (void)hipHostFree(s.h_done);
-        s.h_done = nullptr;
-        if (hipHostMalloc((void**)&s.h_done, cap * sizeof(unsigned int), hipHostMallocMapped) != hipSuccess ||
-            hipHostGetDevicePointer((void**)&s.d_done, s.h_done, 0) != hipSuccess) {
+        unsigned int* h = nullptr;
+        unsigned int* dp = nullptr;
+        if (hipHostMalloc((void**)&h, cap * sizeof(unsigned int), hipHostMallocMapped) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&dp, h, 0) != hipSuccess) {
             (void)hipGetLastError();
-            s.h_done = nullptr;
-            s.cap_done = 0;
+            if (h) (void)hipHostFree(h);
             set_error("batch: mapped host allocation failed");
             return TC_LCC_OUT_OF_MEMORY;
         }
-        memset(s.h_done, 0, cap * sizeof(unsigned int));
+        memset(h, 0, cap * sizeof(unsigned int));
+        if (s.h_done) (void)hipHostFree(s.h_done);
+        s.h_done = h;
+        s.d_done = dp;
         s.cap_done = cap;
-        changed = true;
+        drop_execs(s);
     }
     if (graphs > s.cap_graphs) {
-        size_t cap = std::max<size_t>(graphs, 2 * s.cap_graphs);
-        if (s.d_graphs) pool->release(s.d_graphs);
+        const size_t cap = std::max<size_t>(graphs, 2 * s.cap_graphs);
         void* p = nullptr;
         tc_lcc_status st = pool->alloc(cap * sizeof(BatchGraph), &p);
         if (st != TC_LCC_OK) return st;
-        s.d_graphs = (BatchGraph*)p;
-        if (s.h_graphs) (void)hipHostFree(s.h_graphs);
-        s.h_graphs = nullptr;
-        if (hipHostMalloc((void**)&s.h_graphs, cap * sizeof(BatchGraph), hipHostMallocDefault) != hipSuccess) {
+        BatchGraph* h = nullptr;
+        if (hipHostMalloc((void**)&h, cap * sizeof(BatchGraph), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
+            pool->release(p);
             set_error("batch: pinned host allocation failed");
             return TC_LCC_OUT_OF_MEMORY;
         }
+        if (s.d_graphs) pool->release(s.d_graphs);
+        if (s.h_graphs) (void)hipHostFree(s.h_graphs);
+        s.d_graphs = (BatchGraph*)p;
+        s.h_graphs = h;
         s.cap_graphs = cap;
-        changed = true;
+        drop_execs(s);
     }
     if (!s.d_hdr) {
         void* p = nullptr;
         tc_lcc_status st = pool->alloc(sizeof(BatchHeader), &p);
         if (st != TC_LCC_OK) return st;
-        s.d_hdr = (BatchHeader*)p;
-        if (hipHostMalloc((void**)&s.h_hdr, sizeof(BatchHeader), hipHostMallocDefault) != hipSuccess) {
+        BatchHeader* h = nullptr;
+        if (hipHostMalloc((void**)&h, sizeof(BatchHeader), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
+            pool->release(p);
             set_error("batch: pinned host allocation failed");
             return TC_LCC_OUT_OF_MEMORY;
         }
-        changed = true;
+        s.d_hdr = (BatchHeader*)p;
+        s.h_hdr = h;
+        drop_execs(s);
     }
     if (scratch > s.cap_scratch) {
-        size_t cap = std::max<size_t>(scratch, s.cap_scratch + s.cap_scratch / 2);
-        if (s.d_scratch) pool->release(s.d_scratch);
+        const size_t cap = std::max<size_t>(scratch, s.cap_scratch + s.cap_scratch / 2);
         void* p = nullptr;
         tc_lcc_status st = pool->alloc(cap * sizeof(unsigned long long), &p);
         if (st != TC_LCC_OK) return st;
+        k_batch_clear<<<(unsigned)std::min<size_t>((cap + 255) / 256, 4096), 256, 0, s.stream>>>(
+            (unsigned long long*)p, cap);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s.stream);
+            pool->release(p);
+            set_error("batch: clearing new counters failed: %s", hipGetErrorString(e));
+            return TC_LCC_DEVICE_ERROR;
+        }
+        if (s.d_scratch) pool->release(s.d_scratch);
         s.d_scratch = (unsigned long long*)p;
         s.cap_scratch = cap;
-        k_batch_clear<<<(unsigned)std::min<size_t>((cap + 255) / 256, 4096), 256, 0, s.stream>>>(s.d_scratch, cap);
-        TCL_HIP(hipGetLastError());
-        changed = true;
+        drop_execs(s);
     }
-    if (changed) drop_execs(s);
     return TC_LCC_OK;
 }
 
@@ -433,6 +446,30 @@ void finish_slot(Slot& s) {
 
 }  // namespace
 
+tc_lcc_status batch_engine_create(tc_lcc_ctx ctx) {
+    ctx->batch = new (std::nothrow) Engine();
+    if (!ctx->batch) {
+        set_error("batch: engine allocation failed");
+        return TC_LCC_OUT_OF_MEMORY;
+    }
+    return TC_LCC_OK;
+}
+
+std::mutex& batch_mutex(tc_lcc_ctx ctx) { return engine(ctx)->mu; }
+
+tc_lcc_status batch_fence_graph(tc_lcc_ctx ctx, tc_lcc_graph g, hipStream_t st) {
+    Engine* e = engine(ctx);
+    for (Slot& s : e->slots) {
+        if (!s.busy || s.stream == st) continue;
+        for (tc_lcc_graph x : s.graphs)
+            if (x == g) {
+                TCL_HIP(hipStreamWaitEvent(st, s.ev, 0));
+                break;
+            }
+    }
+    return TC_LCC_OK;
+}
+
 void batch_engine_destroy(tc_lcc_ctx ctx) {
     if (!ctx->batch) return;
     Engine* e = (Engine*)ctx->batch;
@@ -456,6 +493,18 @@ void batch_engine_destroy(tc_lcc_ctx ctx) {
 
 using namespace tcl;
 
+namespace {
+
+// What a submission needs of a graph's schedule, read under the graph's lock (a tc_lcc_run
+// after a tuning change may rebuild the schedule; it first waits for the batches that hold
+// the graph, and it cannot start while a submission holds the engine's lock).
+struct Plan {
+    int64_t heavy = 0, light = 0;
+    bool solo = false;
+};
+
+}  // namespace
+
 extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs,
                                              uint64_t* const* tri, double* const* lcc, tc_lcc_ticket* out) {
     if (!ctx || count <= 0 || !graphs || !tri || !out) {
@@ -469,7 +518,14 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         }
     }
     TCL_HIP(hipSetDevice(ctx->device));
+    int grab = 16, heavy_bits = kBigWorkBits;
+    {
+        std::lock_guard<std::mutex> tl(ctx->mu);
+        if (ctx->tuning.batch_grab > 0) grab = std::min(ctx->tuning.batch_grab, kWave);  // a lane per vertex of a grab
+        if (ctx->tuning.batch_heavy_bits > 0) heavy_bits = ctx->tuning.batch_heavy_bits;
+    }
     Engine* e = engine(ctx);
+    // the engine's lock is held for the whole submission (lock order: engine, then graph)
     std::unique_lock<std::mutex> lk(e->mu);
     // a free slot; if all are busy, wait for the oldest submission
     Slot* s = nullptr;
@@ -495,16 +551,26 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
 
     // order: 4-byte-offset graphs first, then 8-byte ones; graphs with vertices beyond the
     // LDS table (global-memory path) run through the single-graph launches instead
+    std::vector<Plan> plan((size_t)count);
     std::vector<int> ord4, ord8, solo;
     uint32_t need = 0;
     size_t scratch = 0;
     for (int i = 0; i < count; ++i) {
-        const GraphDev& d = graphs[i]->d;
+        tc_lcc_graph g = graphs[i];
+        std::lock_guard<std::mutex> gl(g->mu);
+        const GraphDev& d = g->d;
         const uint32_t r = region_need(d);
+        Plan& p = plan[(size_t)i];
         if (d.n_global > 0 || d.n_list > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
+            p.solo = true;
             solo.push_back(i);
             continue;
         }
+        // heavy: the leading work classes, those with >= 2^(heavy_bits - 1) probes
+        int64_t big = 0;
+        for (int c = 0; c <= 40 - heavy_bits && c < 48; ++c) big += d.class_count[c];
+        p.heavy = big;
+        p.light = d.n_block - big + d.n_wave;
         need = std::max(need, r);
         scratch += (size_t)d.n;
         (d.off_bytes == 4 ? ord4 : ord8).push_back(i);
@@ -523,19 +589,31 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), (size_t)count, std::max<size_t>(scratch, 1));
     if (st != TC_LCC_OK) return st;
 
-    int grab = 16, heavy_bits = kBigWorkBits;
-    {
-        std::lock_guard<std::mutex> tl(ctx->mu);
-        if (ctx->tuning.batch_grab > 0) grab = std::min(ctx->tuning.batch_grab, kWave);  // a lane per vertex of a grab
-        if (ctx->tuning.batch_heavy_bits > 0) heavy_bits = ctx->tuning.batch_heavy_bits;
-    }
+    // reserve the slot before anything is launched on it: from here on the graphs count as
+    // in flight, and an error after a launch waits for the slot's stream before it returns
     const uint32_t seq = e->next_seq++;
+    s->busy = true;
+    s->seq = seq;
+    s->count = count;
+    s->ticket = e->next_ticket++;
+    s->graphs.assign(graphs, graphs + count);
+    for (int i = 0; i < count; ++i) graphs[i]->inflight++;
+    ctx->tickets_inflight++;
+    auto fail = [&](tc_lcc_status why) {
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipGetLastError();
+        finish_slot(*s);
+        ctx->tickets_inflight--;
+        return why;
+    };
+
     int64_t heavy = 0, light = 0, heavy4 = 0, light4 = 0, chunk = 0;
     size_t soff = 0;
     int k = 0;
     for (int pass = 0; pass < 2; ++pass) {
         for (int i : (pass == 0 ? ord4 : ord8)) {
             const GraphDev& d = graphs[i]->d;
+            const Plan& p = plan[(size_t)i];
             BatchGraph& b = s->h_graphs[k++];
             b.out_off = d.out_off;
             b.adj = d.adj;
@@ -550,11 +628,8 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
             b.tri = (unsigned long long*)tri[i];
             b.lcc = lcc ? lcc[i] : nullptr;
             b.n = d.n;
-            // heavy: the leading work classes, those with >= 2^(heavy_bits - 1) probes
-            int64_t big = 0;
-            for (int c = 0; c <= 40 - heavy_bits && c < 48; ++c) big += d.class_count[c];
-            b.heavy = big;
-            b.light = d.n_block - big + d.n_wave;
+            b.heavy = p.heavy;
+            b.light = p.light;
             b.heavy_base = heavy;
             b.light_base = light;
             b.chunk_base = chunk;
@@ -588,30 +663,30 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     if (nb > 0) {
         hipGraphExec_t exec = nullptr;
         st = capture(*s, region, !ord4.empty(), !ord8.empty(), grid_class(heavy, light), ctx->cu_count, &exec);
-        if (st != TC_LCC_OK) return st;
-        TCL_HIP(hipMemcpyAsync(s->d_graphs, s->h_graphs, (size_t)nb * sizeof(BatchGraph), hipMemcpyHostToDevice,
-                               s->stream));
-        TCL_HIP(hipMemcpyAsync(s->d_hdr, s->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s->stream));
-        TCL_HIP(hipGraphLaunch(exec, s->stream));
+        if (st != TC_LCC_OK) return fail(st);
+        if (hipMemcpyAsync(s->d_graphs, s->h_graphs, (size_t)nb * sizeof(BatchGraph), hipMemcpyHostToDevice,
+                           s->stream) != hipSuccess ||
+            hipMemcpyAsync(s->d_hdr, s->h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+            hipGraphLaunch(exec, s->stream) != hipSuccess) {
+            set_error("tc_lcc_batch_submit: launch failed: %s", hipGetErrorString(hipGetLastError()));
+            return fail(TC_LCC_DEVICE_ERROR);
+        }
     }
     // graphs beyond the batched launch's LDS slices: the single-graph launches, on this slot's
     // stream, leaving one block slot per CU free so that other slots' batches keep running
     for (int i : solo) {
-        lk.unlock();
-        st = run_graph(graphs[i], tri[i], lcc ? lcc[i] : nullptr, s->stream, 1);
-        lk.lock();
-        if (st != TC_LCC_OK) return st;
+        st = run_graph(graphs[i], tri[i], lcc ? lcc[i] : nullptr, s->stream, 1, true);
+        if (st != TC_LCC_OK) return fail(st);
         k_batch_mark<<<1, 64, 0, s->stream>>>(s->d_done, i, seq);
-        TCL_HIP(hipGetLastError());
+        if (hipGetLastError() != hipSuccess) {
+            set_error("tc_lcc_batch_submit: flag launch failed");
+            return fail(TC_LCC_DEVICE_ERROR);
+        }
     }
-    TCL_HIP(hipEventRecord(s->ev, s->stream));
-    s->busy = true;
-    s->seq = seq;
-    s->count = count;
-    s->ticket = e->next_ticket++;
-    s->graphs.assign(graphs, graphs + count);
-    for (int i = 0; i < count; ++i) graphs[i]->inflight++;
-    ctx->tickets_inflight++;
+    if (hipEventRecord(s->ev, s->stream) != hipSuccess) {
+        set_error("tc_lcc_batch_submit: event record failed");
+        return fail(TC_LCC_DEVICE_ERROR);
+    }
     *out = s->ticket;
     return TC_LCC_OK;
 }

@@ -1027,13 +1027,15 @@ int32_t table_slots(int probe, int32_t dplus_max) {
 tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st) {
     GraphDev& d = g->d;
     const int probe = resolve_probe(tn.probe, d.n);
-    d.hash_slots = table_slots(probe, d.max_dplus);
+    // the graph's schedule fields change only once the new schedule is complete, so a failed
+    // rebuild leaves the previous one whole
+    const int32_t slots = table_slots(probe, d.max_dplus);
     const bool sorted = probe == TC_LCC_PROBE_SORTED || probe == TC_LCC_PROBE_MERGE;
-    const int32_t block_cap = sorted ? d.hash_slots : hash_capacity(d.hash_slots);
+    const int32_t block_cap = sorted ? slots : hash_capacity(slots);
     // beyond the hash, a block's table still holds a sorted list of as many entries as it has
     // slots (not with the hash-only probe): such vertices get a launch of their own
-    const int32_t list_cap = probe == TC_LCC_PROBE_HASH ? block_cap : d.hash_slots;
-    int32_t wave_cap = sorted ? d.hash_slots / kWavesPerBlock : hash_capacity(d.hash_slots / kWavesPerBlock);
+    const int32_t list_cap = probe == TC_LCC_PROBE_HASH ? block_cap : slots;
+    int32_t wave_cap = sorted ? slots / kWavesPerBlock : hash_capacity(slots / kWavesPerBlock);
     if (tn.wave_outdeg_max > 0 && tn.wave_outdeg_max < wave_cap) wave_cap = tn.wave_outdeg_max;
     Temps tmp{g->ctx->pool.get(), {}};
     const size_t n = (size_t)d.n;
@@ -1066,20 +1068,19 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
         return TC_LCC_DEVICE_ERROR;
     }
     int64_t nb = 0;
-    for (int c = 0; c < kClassWave; ++c) {
-        nb += (int64_t)hc[c];
-        d.class_count[c] = (int64_t)hc[c];
-    }
-    d.n_block = nb;
-    d.n_wave = (int64_t)hc[kClassWave];
-    d.n_list = (int64_t)hc[kClassList];
-    d.n_global = (int64_t)hc[kClassGlobal];
-    const int64_t active = nb + d.n_wave + d.n_list + d.n_global;
+    for (int c = 0; c < kClassWave; ++c) nb += (int64_t)hc[c];
+    const int64_t active = nb + (int64_t)hc[kClassWave] + (int64_t)hc[kClassList] + (int64_t)hc[kClassGlobal];
     if (active > 0) {
         k_vlist<<<grid_for(active, kB, 4096), kB, 0, st>>>(res, active, d.bits, d.vlist);
         TCL_HIP(hipGetLastError());
     }
     TCL_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < kClassWave; ++c) d.class_count[c] = (int64_t)hc[c];
+    d.n_block = nb;
+    d.n_wave = (int64_t)hc[kClassWave];
+    d.n_list = (int64_t)hc[kClassList];
+    d.n_global = (int64_t)hc[kClassGlobal];
+    d.hash_slots = slots;
     d.sched_probe = probe;
     return TC_LCC_OK;
 }

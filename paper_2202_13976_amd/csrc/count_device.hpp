@@ -553,8 +553,11 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
     // ---- flush the per-entry counters of N+(v)
     if (mode == TC_LCC_PROBE_HASH) {
         for (int s = gtid; s < tb.T; s += gsize) {
+            // an empty slot (key -1) never matches a candidate, so its counter is 0; the key
+            // test keeps the flush in bounds without resting on that
             const uint32_t c = tb.cnt[s];
-            if (c) atomicAdd(&a.t[tb.keys[s]], (unsigned long long)c);
+            const int32_t key = tb.keys[s];
+            if (c && key >= 0) atomicAdd(&a.t[key], (unsigned long long)c);
         }
     } else {
         for (int j = gtid; j < dv; j += gsize) {

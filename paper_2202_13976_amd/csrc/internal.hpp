@@ -52,11 +52,14 @@ class Pool {
     uint64_t pooled() const { return pooled_; }
     uint64_t budget() const { return budget_; }
     static size_t round(size_t bytes);
+    // failure injection: the next `after` allocations succeed, the one after fails (< 0: off)
+    void fail_after(int64_t after);
 
    private:
     int device_;
     uint64_t budget_;
     uint64_t in_use_ = 0, pooled_ = 0;
+    int64_t fail_after_ = -1;
     std::mutex mu_;
     std::multimap<size_t, void*> free_;
     std::unordered_map<void*, size_t> live_;
@@ -155,10 +158,17 @@ tc_lcc_status launch_epilogue(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStr
 tc_lcc_status launch_zero_counts(tc_lcc_graph g, hipStream_t st);
 
 // batch.hip
+tc_lcc_status batch_engine_create(tc_lcc_ctx ctx);
 void batch_engine_destroy(tc_lcc_ctx ctx);
+// the batch engine's lock; it is taken before any graph's lock
+std::mutex& batch_mutex(tc_lcc_ctx ctx);
+// make st wait for every batch in flight that holds g (caller holds batch_mutex)
+tc_lcc_status batch_fence_graph(tc_lcc_ctx ctx, tc_lcc_graph g, hipStream_t st);
 
-// api.cpp: the single-graph run of tc_lcc_run, with launch_count's spare_per_cu
-tc_lcc_status run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu);
+// api.cpp: the single-graph run of tc_lcc_run, with launch_count's spare_per_cu;
+// engine_locked: the caller holds batch_mutex (tc_lcc_batch_submit)
+tc_lcc_status run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu,
+                        bool engine_locked = false);
 
 // tuning defaults
 tc_lcc_tuning default_tuning();

@@ -51,6 +51,8 @@ def _load():
         lib.synth_permutation.restype = None
         lib.synth_splitmix64_at.argtypes = [u64, u64]
         lib.synth_splitmix64_at.restype = u64
+        lib.synth_splitmix64_fill.argtypes = [u64, u64, i64, ctypes.c_void_p]
+        lib.synth_splitmix64_fill.restype = None
         _lib = lib
     return _lib
 
@@ -62,6 +64,13 @@ def _p32(a: np.ndarray):
 def splitmix64_at(state: int, k: int) -> int:
     """k-th output of SplitMix64 started from `state` (exposed for its known-answer test)."""
     return int(_load().synth_splitmix64_at(state & (2**64 - 1), k))
+
+
+def splitmix64_fill(state: int, k0: int, count: int) -> np.ndarray:
+    """Outputs k0 .. k0 + count - 1 of SplitMix64 started from `state`."""
+    out = np.empty(count, dtype=np.uint64)
+    _load().synth_splitmix64_fill(state & (2**64 - 1), k0, count, out.ctypes.data)
+    return out
 
 
 def permutation(n: int, seed: int) -> np.ndarray:
@@ -138,6 +147,32 @@ def serving_specs(count: int = 64, seed: int = 9, lo_scale: int = 10, hi_scale: 
         n = int(round(2.0 ** (lo_scale + u0 * (hi_scale - lo_scale))))
         specs.append(("rmat", n, edge_factor * n, 5000 + i))
     return specs
+
+
+def dense_core(parts: int, size: int, drop: float, periphery_scale: int, seed: int):
+    """A dense graph that is not a clique, with a sparse periphery.
+
+    Core: vertices [0, parts * size) in `parts` parts of `size`; every pair in different parts
+    is joined except a fraction `drop` of them (pair i of the row-major upper triangle is
+    dropped when output i of the seed's stream falls below drop * 2^64).  Periphery: R-MAT
+    pairs (edge factor 8) over the next 2^periphery_scale ids, each periphery vertex p also
+    joined to core vertices 7 p and 13 p + 1 (mod the core size).  Returns (n, src, dst).
+    """
+    nc = parts * size
+    iu, ju = np.triu_indices(nc, 1)
+    keep = (iu // size) != (ju // size)
+    if drop > 0:
+        r = splitmix64_fill(sub_seed_py(seed), 0, len(iu))
+        keep &= r >= np.uint64(int(drop * 2.0**64))
+    cs, cd = iu[keep].astype(np.int32), ju[keep].astype(np.int32)
+    npp = 1 << periphery_scale if periphery_scale > 0 else 0
+    parts_s, parts_d = [cs], [cd]
+    if npp:
+        ps, pd = rmat(npp, 8 * npp, seed + 1)
+        p = np.arange(npp, dtype=np.int64)
+        parts_s += [ps + nc, (p + nc).astype(np.int32), (p + nc).astype(np.int32)]
+        parts_d += [pd + nc, ((7 * p) % nc).astype(np.int32), ((13 * p + 1) % nc).astype(np.int32)]
+    return nc + npp, np.concatenate(parts_s).astype(np.int32), np.concatenate(parts_d).astype(np.int32)
 
 
 def make(spec):

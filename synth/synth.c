@@ -37,6 +37,11 @@ enum { TAG_RMAT = 1, TAG_PERM = 2, TAG_ER = 3 };
 
 uint64_t synth_splitmix64_at(uint64_t state, uint64_t k) { return sm_at(state, k); }
 
+/* outputs k0 .. k0 + count - 1 of the stream `state` */
+void synth_splitmix64_fill(uint64_t state, uint64_t k0, int64_t count, uint64_t* out) {
+    for (int64_t i = 0; i < count; ++i) out[i] = sm_at(state, k0 + (uint64_t)i);
+}
+
 /* uniform integer in [0, bound) from a 64-bit draw (multiply-high; bias < bound / 2^64) */
 static inline uint64_t bounded(uint64_t r, uint64_t bound) {
     return (uint64_t)(((unsigned __int128)r * bound) >> 64);
