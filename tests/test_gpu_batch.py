@@ -1,5 +1,8 @@
 """Batched path: many graphs in one persistent launch give exactly the single-graph results."""
+import hashlib
 import itertools
+import json
+import os
 import time
 
 import numpy as np
@@ -34,6 +37,28 @@ def outputs(graphs):
     tris = [torch.full((g.n,), -1, dtype=torch.int64, device="cuda") for g in graphs]
     lccs = [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for g in graphs]
     return tris, lccs
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden_lines(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)["graphs"]
+
+
+def host_vectors(tensors):
+    """Device tensors -> host numpy arrays, with one copy for all of them."""
+    sizes = [t.numel() for t in tensors]
+    flat = torch.cat([t.reshape(-1) for t in tensors]).cpu().numpy()
+    return np.split(flat, np.cumsum(sizes)[:-1])
+
+
+def line_of(m, t, lcc):
+    """The stored line of one graph: m, triangles, sha256(t u64 LE || LCC f64 LE)[:16]."""
+    t = t.astype(np.uint64)
+    h = hashlib.sha256(t.astype("<u8").tobytes() + lcc.astype("<f8").tobytes()).hexdigest()[:16]
+    return f"{m} {int(t.sum()) // 3} {h}"
 
 
 def small_specs(k, seed):
@@ -199,5 +224,39 @@ def test_batch_degenerate_and_repeated_graphs(ctx):
         t_ref, l_ref = oracle.tc_lcc(n, s, d)
         np.testing.assert_array_equal(tri.cpu().numpy().astype(np.uint64), t_ref)
         assert lcc.cpu().numpy().tobytes() == l_ref.tobytes()
+    for g in graphs:
+        g.free()
+
+
+def test_full_4096_graph_batch_against_oracle(ctx):
+    """The many-small-graphs workload at full size (4096 graphs, as the benchmark runs it): one
+    batched submission and the loop of single-graph runs, every graph's full t and LCC vectors
+    against the oracle's stored per-graph digests."""
+    specs = synth.batch_specs()
+    ref = golden_lines("batch4096_seed7")
+    assert len(ref) == len(specs)
+    print(f"[gpu] full batch: building {len(specs)} graphs", flush=True)
+    graphs, ms = [], []
+    for spec in specs:
+        n, s, d = synth.make(spec)
+        g = build(ctx, n, s, d, 4)
+        graphs.append(g)
+        ms.append(int(g.info().m))
+    tris, lccs = outputs(graphs)
+    print("[gpu] full batch: one submission", flush=True)
+    tk = ctx.batch_submit(graphs, tris, lccs)
+    done, nd = ctx.batch_poll(tk, block=True)
+    assert done and nd == len(graphs)
+    got_t, got_l = host_vectors(tris), host_vectors(lccs)
+    bad = [i for i in range(len(graphs)) if line_of(ms[i], got_t[i], got_l[i]) != ref[i]]
+    assert not bad, f"batched: {len(bad)} graphs differ from the oracle, first {bad[:8]}"
+    print("[gpu] full batch: loop of single-graph runs", flush=True)
+    tris2, lccs2 = outputs(graphs)
+    for g, t, l in zip(graphs, tris2, lccs2):
+        g.run(t, l)
+    torch.cuda.synchronize()
+    got_t, got_l = host_vectors(tris2), host_vectors(lccs2)
+    bad = [i for i in range(len(graphs)) if line_of(ms[i], got_t[i], got_l[i]) != ref[i]]
+    assert not bad, f"single-graph loop: {len(bad)} graphs differ from the oracle, first {bad[:8]}"
     for g in graphs:
         g.free()

@@ -4,7 +4,12 @@ Counts are integers and must match exactly; LCC is one IEEE division of the same
 exact integers on both sides, so it must match bit for bit too (tolerance 0).
 Every case prints its name before it touches the GPU.
 """
+import hashlib
 import itertools
+import json
+import math
+import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -57,6 +62,39 @@ def check(ctx, n, s, d, label, **kw):
     return t_ref
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+def digests(t, l):
+    return (hashlib.sha256(np.ascontiguousarray(t, dtype="<u8").tobytes()).hexdigest(),
+            hashlib.sha256(np.ascontiguousarray(l, dtype="<f8").tobytes()).hexdigest())
+
+
+def check_golden(name, t, l, n, s, d):
+    """Whole-vector comparison with the oracle's stored digests (written by
+    tests/golden/make_golden.py from oracle/ alone); on a mismatch, the oracle recomputes
+    sampled vertices one by one to name the first differences."""
+    ref = golden(name)
+    assert ref["n"] == n and ref["raw_pairs"] == len(s)
+    assert t[:16].tolist() == ref["t_head"]
+    assert [float(x).hex() for x in l[:16]] == ref["lcc_head"]
+    assert int(t.sum()) // 3 == ref["triangles"]
+    dt, dl = digests(t, l)
+    if dt != ref["sha256_t_u64le"]:
+        g = oracle.csr(n, s, d)
+        rng = np.random.default_rng(1)
+        pick = np.unique(np.concatenate([rng.choice(n, min(n, 400), replace=False), np.argsort(g.deg)[-16:]]))
+        want = oracle.tc_vertices(g, pick)
+        bad = pick[want != t[pick]]
+        raise AssertionError(f"{name}: t differs from the oracle's digest; sampled mismatches at {bad[:8]}")
+    assert dl == ref["sha256_lcc_f64le"], f"{name}: LCC bits differ from the oracle's digest"
+
+
 def arr(pairs):
     if not pairs:
         return np.zeros(0, np.int32), np.zeros(0, np.int32)
@@ -79,30 +117,79 @@ def test_rmat_small(ctx, scale, ob):
 
 
 def test_rmat_s20_full(ctx):
-    """R-MAT scale 20, edge factor 16, int64 offsets: every vertex against the oracle."""
+    """R-MAT scale 20, edge factor 16, int64 offsets: every vertex against the oracle (its
+    stored full-vector digests)."""
     n, s, d = synth.rmat_scale(20, 16, seed=1)
-    check(ctx, n, s, d, "RMAT S20 EF16", offset_bytes=8)
+    say(f"[gpu] RMAT S20 EF16: n={n} pairs={len(s)}")
+    t, l = gpu_run(ctx, n, s, d, offset_bytes=8)
+    check_golden("rmat_s20_ef16_seed1", t, l, n, s, d)
 
 
-def test_rmat_s23_sampled(ctx):
-    """R-MAT scale 23 at full size, as the benchmark runs it: sampled vertices against the
-    oracle one by one (all hubs among them), plus properties that hold at any size."""
+def test_rmat_s23_full(ctx):
+    """R-MAT scale 23 at full size, as the benchmark runs it: all 8,388,608 counts and LCC
+    values against the oracle's stored digests."""
     n, s, d = synth.rmat_scale(23, 16, seed=1)
     say("[gpu] RMAT S23 EF16 full size")
     t, l = gpu_run(ctx, n, s, d, offset_bytes=8)
-    g = oracle.csr(n, s, d)
-    deg = g.deg
-    rng = np.random.default_rng(23)
-    sample = np.unique(np.concatenate([rng.choice(n, 400, replace=False), np.argsort(deg)[-12:],
-                                       np.nonzero(deg == 2)[0][:20]]))
-    want = oracle.tc_vertices(g, sample)
-    np.testing.assert_array_equal(t[sample], want)
-    du = deg.astype(np.uint64)
-    assert np.all(t <= du * (du - np.uint64(1)) // np.uint64(2) + (du < 2))
-    assert int(t.sum()) % 3 == 0
-    with np.errstate(divide="ignore", invalid="ignore"):
-        ref = np.where(deg >= 2, (2 * t.astype(np.float64)) / (deg.astype(np.float64) * (deg - 1)), 0.0)
-    assert l.tobytes() == ref.tobytes()
+    check_golden("rmat_s23_ef16_seed1", t, l, n, s, d)
+
+
+def test_dense_core_list_and_global_paths(ctx):
+    """A dense core that is not a clique (13 parts of 200, 5 % of the cross pairs dropped) with
+    an R-MAT periphery: |N+(v)| passes 2048 at the lowest-ranked core vertices and most
+    candidates of a core list miss.  The default probe sends those lists to the block table
+    as a sorted list, the hash-only probe to the global-memory path (the miss branch of both
+    runs); the sorted and hybrid probes take them in LDS.  Every vertex against the oracle's
+    digests."""
+    name = "dense_core_13x200_drop5_p11_seed61"
+    n, s, d = synth.dense_core(13, 200, 0.05, 11, 61)
+    probe0 = ctx.tuning().probe
+    try:
+        for probe, ob in [(pkg.PROBE_AUTO, 8), (pkg.PROBE_HASH, 4), (pkg.PROBE_SORTED, 8), (pkg.PROBE_MERGE, 4)]:
+            say(f"[gpu] {name} probe={probe} offsets={ob}")
+            ctx.set_tuning(probe=probe)
+            g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=ob)
+            try:
+                info = g.info()
+                assert info.max_out_degree > 2048
+                assert (info.global_vertices > 0) == (probe == pkg.PROBE_HASH)
+                tri, lcc = g.run()
+                torch.cuda.synchronize()
+            finally:
+                g.free()
+            check_golden(name, tri.cpu().numpy().astype(np.uint64), lcc.cpu().numpy(), n, s, d)
+    finally:
+        ctx.set_tuning(probe=probe0)
+
+
+def test_multipartite_beyond_every_table(ctx):
+    """Complete 50-partite graph with parts of 100: all degrees equal, so ranks follow ids, the
+    first part has no in-edges, and the first vertex of every later part has |N+(v)| of up to
+    n - 2 * 100 = 4800, beyond the LDS table even as a sorted list: the default probe searches
+    those lists in HBM, and a candidate in the vertex's own part misses.  Closed form
+    t = C(4900, 2) - 49 C(100, 2), LCC = 2t/(d(d-1)) (pinned in the oracle tests), and the
+    oracle on sampled vertices."""
+    k, size = 50, 100
+    nn = k * size
+    iu, ju = np.triu_indices(nn, 1)
+    keep = (iu // size) != (ju // size)
+    s, d = iu[keep].astype(np.int32), ju[keep].astype(np.int32)
+    say(f"[gpu] complete {k}-partite, parts of {size}")
+    g = ctx.build_csr(nn, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    try:
+        assert g.info().global_vertices > 0
+        tri, lcc = g.run()
+        torch.cuda.synchronize()
+    finally:
+        g.free()
+    t = tri.cpu().numpy().astype(np.uint64)
+    deg = (k - 1) * size
+    want = math.comb(deg, 2) - (k - 1) * math.comb(size, 2)
+    assert np.all(t == want)
+    assert np.all(lcc.cpu().numpy() == float(Fraction(2 * want, deg * (deg - 1))))
+    og = oracle.csr(nn, s, d)
+    pick = np.arange(0, nn, 97)
+    np.testing.assert_array_equal(oracle.tc_vertices(og, pick), t[pick])
 
 
 # ------------------------------------------------------------------ strategies (results never depend on them)

@@ -1,5 +1,8 @@
 """Serving loop: requests admitted by HBM budget and batched as they arrive give exactly the
 results of each graph counted alone."""
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
@@ -130,3 +133,45 @@ def test_over_budget_and_unknown(ctx, pool):
         server.poll(424242)
     assert e.value.status == pkg.INVALID_ARGUMENT
     server.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_serving_pool_at_full_size_against_oracle(ctx):
+    """The serving workload's own pool (64 R-MAT EF16 graphs, n log-uniform in [2^10, 2^21]):
+    a Poisson stream through the continuous-batching server and a pass through the plain
+    server, every served output's full t and LCC vectors against the oracle's stored digests."""
+    with open(os.path.join(GOLDEN, "serving64_seed9.json")) as f:
+        ref = json.load(f)["graphs"]
+    specs = synth.serving_specs(count=64, seed=9)
+    print(f"[gpu] serving pool: building {len(specs)} graphs", flush=True)
+    graphs = []
+    for spec in specs:
+        n, s, d = synth.make(spec)
+        graphs.append(ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()))
+    ms = [int(g.info().m) for g in graphs]
+
+    def verify(k, tri, lcc, what):
+        t = tri.cpu().numpy().astype(np.uint64)
+        l = lcc.cpu().numpy()
+        h = hashlib.sha256(t.astype("<u8").tobytes() + l.astype("<f8").tobytes()).hexdigest()[:16]
+        assert f"{ms[k]} {int(t.sum()) // 3} {h}" == ref[k], f"{what}: graph {k} differs from the oracle"
+
+    picks = synth.choices(240, len(graphs), seed=13)
+    gaps = synth.poisson_gaps(240, 2000.0, seed=11)
+    print("[gpu] serving pool: 240 requests through the batching server", flush=True)
+    server = pkg.Server(ctx, budget_bytes=8 << 30, max_inflight=4, max_batch=4096)
+    outs, infos = drive(server, graphs, picks, gaps)
+    server.close()
+    for (k, tri, lcc), inf in zip(outs, infos):
+        verify(k, tri, lcc, "batched server")
+    assert max(inf.batch_size for inf in infos) > 1
+    print("[gpu] serving pool: every graph once through the plain server", flush=True)
+    plain = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=1)
+    outs, _ = drive(plain, graphs, list(range(len(graphs))), [0.0] * len(graphs))
+    plain.close()
+    for k, tri, lcc in outs:
+        verify(k, tri, lcc, "plain server")
+    for g in graphs:
+        g.free()
