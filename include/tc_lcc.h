@@ -110,9 +110,24 @@ typedef struct {
     int32_t table_slots;      /* LDS table slots of one block */
     uint64_t push_words;      /* sum over oriented edges (u -> v) of |N+(v)| (whole-list streaming) */
     int64_t global_vertices;  /* active vertices whose N+(v) exceeds the LDS table (searched in HBM) */
+    int32_t directed;         /* 1: built by tc_lcc_build_directed (m, max_degree: its undirected skeleton) */
+    int32_t reserved_;        /* 0 */
 } tc_lcc_graph_stats;
 
 tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);
+
+/* Build the device graph of a DIRECTED input for the directed clustering coefficient of Eq. 1
+ * (Sec. II-D).  Pair e is the edge e_ij from v_i = src[e] to v_j = dst[e] (Sec. II-A);
+ * adj(v_i) is the set of out-neighbours and deg+(v_i) its size.  Self-loops are dropped and
+ * repeats of the same ordered pair count once; (i, j) and (j, i) are two different edges.
+ * The graph stores the undirected skeleton (as tc_lcc_build_csr would build it from the same
+ * pairs) plus, per skeleton edge, which of its two directions the input held, and every
+ * vertex's out-degree.  tc_lcc_run on such a graph computes Eq. 1 (see there);
+ * tc_lcc_run_edges refuses it (UNSUPPORTED); in a batch it takes the single-graph launches.
+ * Arguments, ownership and errors as tc_lcc_build_csr. */
+tc_lcc_status tc_lcc_build_directed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
+                                    const int32_t* dst, int inputs_on_device, int offset_bytes,
+                                    void* hip_stream, tc_lcc_graph* out);
 
 /* Copy the built structure to host memory (for checking the builder).  Every
  * pointer may be NULL to skip that array.
@@ -134,10 +149,26 @@ tc_lcc_status tc_lcc_graph_free(tc_lcc_graph g);
  * tri: device pointer, n uint64: tri[v] = t(v), triangles containing vertex v.
  * lcc: device pointer, n double: 2 t(v) / (d(v) (d(v)-1)) as one IEEE binary64
  *      division of exact integers; 0.0 when d(v) < 2.  May be NULL to skip.
+ * For a graph from tc_lcc_build_directed, Eq. 1 instead: tri[v] = the numerator, the edges
+ *      e_jk with v_j, v_k out-neighbours of v (ordered pairs: e_jk and e_kj count apart), and
+ *      lcc[v] = tri[v] / (deg+(v) (deg+(v)-1)), one IEEE division; 0.0 when deg+(v) < 2.
  * Asynchronous and ordered on hip_stream; the outputs are complete when the
  * stream reaches this point.  Runs of one graph are serialised by the library
  * (they share the graph's scratch counters).  */
 tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, void* hip_stream);
+
+/* Per-edge triangle counts: the entries of C = A A o A (Sec. V-B), c_ij = the triangles that
+ * contain the edge {i, j} = |adj(i) ∩ adj(j)|, together with the per-vertex results of
+ * tc_lcc_run (tri required, lcc may be NULL; same meaning).
+ * edge_src, edge_dst: device int32[m], edge_tri: device uint32[m], m = the graph's undirected
+ *   edge count (tc_lcc_graph_info): edge e joins edge_src[e] < edge_dst[e] (original ids), the
+ *   edges in ascending (edge_src, edge_dst) order, the upper triangle of A row by row; any of
+ *   the three may be NULL to skip it.  c_ij < 2^31 always (it is below the smaller degree).
+ * Temporaries (about 24 bytes per edge) come from the context's pool; the call waits for
+ * hip_stream before it returns.  UNSUPPORTED for a directed graph; OUT_OF_MEMORY or
+ * OVER_BUDGET if the temporaries cannot be had (no output is written then). */
+tc_lcc_status tc_lcc_run_edges(tc_lcc_graph g, uint64_t* tri, double* lcc, int32_t* edge_src, int32_t* edge_dst,
+                               uint32_t* edge_tri, void* hip_stream);
 
 /* ------------------------------------------------------------------ batches */
 
@@ -261,9 +292,11 @@ tc_lcc_status tc_lcc_tuning_load(tc_lcc_ctx ctx, const char* json_path);
 
 /* ------------------------------------------------------------------ profiling */
 
-/* When enabled, tc_lcc_build_csr and tc_lcc_run record HIP events on their stream
- * around each phase; tc_lcc_graph_timings reads the durations of the graph's last
- * build and last run (waiting for the run to finish).  Milliseconds. */
+/* When enabled, the builds and the runs (tc_lcc_run, tc_lcc_run_edges) record HIP events on
+ * their stream around each phase; tc_lcc_graph_timings reads the durations of the graph's last
+ * build and last run (waiting for the run to finish).  Milliseconds.  For tc_lcc_run_edges,
+ * run_count_ms is the extended count kernel and run_epilogue_ms the LCC epilogue plus the
+ * per-edge output (sort into edge order and gather). */
 typedef struct {
     float build_sort_unique_ms; /* canonical keys, radix sort, unique, degrees */
     float build_rank_ms;        /* rank by (degree, id) */
@@ -277,6 +310,16 @@ typedef struct {
 
 tc_lcc_status tc_lcc_set_profiling(tc_lcc_ctx ctx, int enable);
 tc_lcc_status tc_lcc_graph_timings(tc_lcc_graph g, tc_lcc_timings* out);
+
+/* ------------------------------------------------------------------ measurement */
+
+/* Copy `bytes` from src to dst (device pointers of the current device, 16-byte aligned,
+ * bytes a multiple of 16, not overlapping) with a plain streaming kernel: 16-byte vector loads
+ * and stores through the shader cores.  Its rate is the achievable HBM bandwidth that the
+ * count kernel's roofline fraction is also reported against, and its known size scales the
+ * HBM traffic counters.  Asynchronous on hip_stream.  INVALID_ARGUMENT for a null pointer or
+ * a misaligned size or address. */
+tc_lcc_status tc_lcc_hbm_copy(const void* src, void* dst, uint64_t bytes, void* hip_stream);
 
 /* ------------------------------------------------------------------ misc */
 

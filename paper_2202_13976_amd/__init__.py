@@ -41,7 +41,8 @@ class GraphStats(ctypes.Structure):
                 ("staged_entries", ctypes.c_int64), ("block_vertices", ctypes.c_int64),
                 ("count_grid", ctypes.c_int32), ("count_lds_bytes", ctypes.c_int32),
                 ("count_blocks_per_cu", ctypes.c_int32), ("table_slots", ctypes.c_int32),
-                ("push_words", ctypes.c_uint64), ("global_vertices", ctypes.c_int64)]
+                ("push_words", ctypes.c_uint64), ("global_vertices", ctypes.c_int64),
+                ("directed", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class Timings(ctypes.Structure):
@@ -71,12 +72,13 @@ class RequestInfo(ctypes.Structure):
 
 _lib = None
 EXPORTS = [
-    "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_debug_fail_alloc", "tc_lcc_build_csr", "tc_lcc_graph_info",
+    "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_debug_fail_alloc", "tc_lcc_build_csr",
+    "tc_lcc_build_directed", "tc_lcc_run_edges", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
     "tc_lcc_batch_progress", "tc_lcc_autotune", "tc_lcc_tuning_load",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
     "tc_lcc_server_create", "tc_lcc_server_submit", "tc_lcc_server_poll", "tc_lcc_server_destroy",
-    "tc_lcc_status_string", "tc_lcc_last_error",
+    "tc_lcc_hbm_copy", "tc_lcc_status_string", "tc_lcc_last_error",
 ]
 
 
@@ -95,6 +97,8 @@ def lib():
     L.tc_lcc_ctx_memory.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
     L.tc_lcc_debug_fail_alloc.argtypes = [vp, i64]
     L.tc_lcc_build_csr.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+    L.tc_lcc_build_directed.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+    L.tc_lcc_run_edges.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tc_lcc_graph_info.argtypes = [vp, ctypes.POINTER(GraphStats)]
     L.tc_lcc_graph_export.argtypes = [vp, vp, vp, vp, vp]
     L.tc_lcc_graph_free.argtypes = [vp]
@@ -112,6 +116,7 @@ def lib():
     L.tc_lcc_server_submit.argtypes = [vp, vp, vp, vp, ctypes.POINTER(u64)]
     L.tc_lcc_server_poll.argtypes = [vp, u64, i32, ctypes.POINTER(RequestInfo)]
     L.tc_lcc_server_destroy.argtypes = [vp]
+    L.tc_lcc_hbm_copy.argtypes = [vp, vp, u64, vp]
     for name in EXPORTS[:-2]:
         getattr(L, name).restype = st
     L.tc_lcc_status_string.argtypes = [st]
@@ -170,6 +175,25 @@ class Graph:
         _check(lib().tc_lcc_run(self.handle, _dptr(tri), _dptr(lcc), _stream_ptr(stream)), "tc_lcc_run")
         return tri, lcc
 
+    def run_edges(self, tri=None, lcc=None, stream=None, want_lcc: bool = True):
+        """Per-vertex results plus per-edge triangle counts (tc_lcc_run_edges, synchronous):
+        returns (tri, lcc, edge_src, edge_dst, edge_tri) device tensors, edges {src < dst} in
+        ascending (src, dst) order, edge_tri as int32 holding the uint32 counts."""
+        import torch
+        s = self.info()
+        n, m = int(s.n), int(s.m)
+        dev = torch.device("cuda", self.ctx.device)
+        if tri is None:
+            tri = torch.empty(n, dtype=torch.int64, device=dev)
+        if lcc is None and want_lcc:
+            lcc = torch.empty(n, dtype=torch.float64, device=dev)
+        es = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        ed = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        ec = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        _check(lib().tc_lcc_run_edges(self.handle, _dptr(tri), _dptr(lcc), _dptr(es), _dptr(ed), _dptr(ec),
+                                      _stream_ptr(stream)), "tc_lcc_run_edges")
+        return tri, lcc, es[:m], ed[:m], ec[:m]
+
     def export(self):
         """(degree[n], order[n], out_off[n+1], out_adj[m]) on the host, for checking the builder."""
         s = self.info()
@@ -209,7 +233,7 @@ class Context:
         _check(lib().tc_lcc_ctx_create(device, budget_bytes, ctypes.byref(h)), "tc_lcc_ctx_create")
         self.handle = h
 
-    def build_csr(self, n: int, src, dst, offset_bytes: int = 0, stream=None) -> Graph:
+    def build_csr(self, n: int, src, dst, offset_bytes: int = 0, stream=None, _entry: str = "tc_lcc_build_csr") -> Graph:
         """src/dst: int32 torch CUDA tensors (device path) or numpy arrays (host path)."""
         import torch
         if isinstance(src, torch.Tensor):
@@ -225,10 +249,15 @@ class Context:
             on_dev, ps, pd, m = 0, ctypes.c_void_p(s.ctypes.data), ctypes.c_void_p(d.ctypes.data), s.size
             keep = (s, d)
         h = ctypes.c_void_p()
-        _check(lib().tc_lcc_build_csr(self.handle, n, m, ps, pd, on_dev, offset_bytes, _stream_ptr(stream),
-                                      ctypes.byref(h)), "tc_lcc_build_csr")
+        _check(getattr(lib(), _entry)(self.handle, n, m, ps, pd, on_dev, offset_bytes, _stream_ptr(stream),
+                                      ctypes.byref(h)), _entry)
         del keep
         return Graph(self, h)
+
+    def build_directed(self, n: int, src, dst, offset_bytes: int = 0, stream=None) -> Graph:
+        """Directed input (tc_lcc_build_directed): src[e] -> dst[e]; Graph.run then gives the
+        numerator and the clustering coefficient of Eq. 1.  Same argument forms as build_csr."""
+        return self.build_csr(n, src, dst, offset_bytes=offset_bytes, stream=stream, _entry="tc_lcc_build_directed")
 
     def tuning(self) -> Tuning:
         t = Tuning()
@@ -333,6 +362,14 @@ class Server:
         if self.handle:
             _check(lib().tc_lcc_server_destroy(self.handle), "tc_lcc_server_destroy")
             self.handle = None
+
+
+def hbm_copy(src, dst, stream=None):
+    """tc_lcc_hbm_copy: dst[:] = src[:] (device tensors of equal byte size) by the streaming copy
+    kernel, asynchronous on `stream`."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb and src.is_cuda and dst.is_cuda
+    _check(lib().tc_lcc_hbm_copy(_dptr(src), _dptr(dst), nb, _stream_ptr(stream)), "tc_lcc_hbm_copy")
 
 
 def tc_lcc(n: int, src, dst, offset_bytes: int = 0, ctx: Context | None = None):

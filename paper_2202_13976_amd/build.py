@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtc_lcc.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "radix.hip", "build.hip", "count.hip", "batch.hip", "server.cpp", "autotune.cpp"]
+SOURCES = ["api.cpp", "radix.hip", "build.hip", "count.hip", "count_ext.hip", "batch.hip", "server.cpp",
+           "autotune.cpp", "hbm.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -256,9 +256,9 @@ static void graph_release(tc_lcc_graph g) {
     delete g;
 }
 
-extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
-                                          const int32_t* dst, int inputs_on_device, int offset_bytes,
-                                          void* hip_stream, tc_lcc_graph* out) {
+static tc_lcc_status build_common(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
+                                  int inputs_on_device, int offset_bytes, void* hip_stream, tc_lcc_graph* out,
+                                  bool directed) {
     if (!ctx || !out) {
         set_error("tc_lcc_build_csr: null context or out");
         return TC_LCC_INVALID_ARGUMENT;
@@ -292,7 +292,7 @@ extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_i
         tn = ctx->tuning;
         gen = ctx->tuning_gen;
     }
-    tc_lcc_status s = build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, tn, st, g);
+    tc_lcc_status s = build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, tn, st, g, directed);
     if (s == TC_LCC_OK) {
         g->d.sched_gen = gen;
         if (hipEventCreateWithFlags(&g->last_use, hipEventDisableTiming) != hipSuccess ||
@@ -311,6 +311,18 @@ extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_i
     ctx->graphs++;
     *out = g;
     return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
+                                          const int32_t* dst, int inputs_on_device, int offset_bytes,
+                                          void* hip_stream, tc_lcc_graph* out) {
+    return build_common(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, hip_stream, out, false);
+}
+
+extern "C" tc_lcc_status tc_lcc_build_directed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
+                                               const int32_t* dst, int inputs_on_device, int offset_bytes,
+                                               void* hip_stream, tc_lcc_graph* out) {
+    return build_common(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, hip_stream, out, true);
 }
 
 extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out) {
@@ -335,6 +347,8 @@ extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* o
     out->table_slots = g->d.hash_slots;
     out->push_words = g->d.push_words;
     out->global_vertices = g->d.n_global;
+    out->directed = g->d.directed ? 1 : 0;
+    out->reserved_ = 0;
     return TC_LCC_OK;
 }
 
@@ -385,19 +399,21 @@ extern "C" tc_lcc_status tc_lcc_graph_free(tc_lcc_graph g) {
 
 // ------------------------------------------------------------------ one graph
 
-tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu,
-                             bool engine_locked) {
+// The graph's lock held, its last use waited for, and its schedule made current for the
+// context's tuning (a rebuild first waits for the batches that hold the graph).
+static tc_lcc_status prepare_run(tc_lcc_graph g, hipStream_t st, bool engine_locked, tc_lcc_tuning& tn,
+                                 std::unique_lock<std::mutex>& lk, bool allow_rebuild = true) {
     tc_lcc_ctx ctx = g->ctx;
     TCL_HIP(hipSetDevice(ctx->device));
-    tc_lcc_tuning tn;
     uint64_t gen;
     {
-        std::lock_guard<std::mutex> lk(ctx->mu);
+        std::lock_guard<std::mutex> cl(ctx->mu);
         tn = ctx->tuning;
         gen = ctx->tuning_gen;
     }
     std::unique_lock<std::mutex> el;
-    std::unique_lock<std::mutex> lk(g->mu);
+    lk = std::unique_lock<std::mutex>(g->mu);
+    if (!allow_rebuild) gen = g->d.sched_gen;  // the schedule as it stands (results never depend on it)
     if (g->d.sched_gen != gen && !engine_locked) {
         // a schedule rebuild rewrites the vertex list that batches in flight read: take the
         // engine's lock (before the graph's) so that no batch starts meanwhile, and wait for
@@ -413,13 +429,27 @@ tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStre
         if (s != TC_LCC_OK) return s;
         g->d.sched_gen = gen;
     }
-    if (el.owns_lock()) el.unlock();
+    return TC_LCC_OK;
+}
+
+tc_lcc_status tcl::run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st, int spare_per_cu,
+                             bool engine_locked) {
+    tc_lcc_tuning tn;
+    std::unique_lock<std::mutex> lk;
+    tc_lcc_status s = prepare_run(g, st, engine_locked, tn, lk);
+    if (s != TC_LCC_OK) return s;
     mark(g->d, 6, st);
-    tc_lcc_status s = launch_zero_counts(g, st);
+    s = launch_zero_counts(g, st);
     mark(g->d, 7, st);
-    if (s == TC_LCC_OK) s = launch_count(g, tn, spare_per_cu, st);
-    mark(g->d, 8, st);
-    if (s == TC_LCC_OK) s = launch_epilogue(g, tri, lcc, st);
+    if (g->d.directed) {
+        if (s == TC_LCC_OK) s = launch_count_directed(g, st);
+        mark(g->d, 8, st);
+        if (s == TC_LCC_OK) s = launch_epilogue_directed(g, tri, lcc, st);
+    } else {
+        if (s == TC_LCC_OK) s = launch_count(g, tn, spare_per_cu, st);
+        mark(g->d, 8, st);
+        if (s == TC_LCC_OK) s = launch_epilogue(g, tri, lcc, st);
+    }
     mark(g->d, 9, st);
     if (s != TC_LCC_OK) return s;
     TCL_HIP(hipEventRecord(g->last_use, st));
@@ -432,6 +462,130 @@ extern "C" tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, 
         return TC_LCC_INVALID_ARGUMENT;
     }
     return run_graph(g, tri, lcc, (hipStream_t)hip_stream, 0);
+}
+
+namespace {
+
+__global__ void k_zero_u32(uint32_t* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Temporaries from the context's pool, given back when the call returns (it waits for its stream).
+struct CallTemps {
+    Pool* pool;
+    std::vector<void*> held;
+    ~CallTemps() {
+        for (void* p : held) pool->release(p);
+    }
+    template <typename T>
+    tc_lcc_status get(size_t count, T** out) {
+        void* p = nullptr;
+        tc_lcc_status s = pool->alloc(count * sizeof(T) + 16, &p);
+        if (s != TC_LCC_OK) return s;
+        held.push_back(p);
+        *out = (T*)p;
+        return TC_LCC_OK;
+    }
+};
+
+}  // namespace
+
+// Temporaries of the per-edge run: per-position counters, two key buffers for the sort into
+// edge order, the sort's scratch, an error word and the rank of every id.
+struct EdgeTemps {
+    uint32_t* ce = nullptr;
+    uint64_t* keys = nullptr;
+    uint64_t* alt = nullptr;
+    uint8_t* scratch = nullptr;
+    unsigned int* err = nullptr;
+    int32_t* rank = nullptr;
+};
+
+static tc_lcc_status edges_check(tc_lcc_graph g, uint64_t* tri, const char* who) {
+    if (!g || !tri) {
+        set_error("%s: null graph or output", who);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (g->d.directed) {
+        set_error("%s: per-edge counts are defined here for undirected graphs", who);
+        return TC_LCC_UNSUPPORTED;
+    }
+    return TC_LCC_OK;
+}
+
+// The per-edge run on given temporaries; waits for the stream before it returns.
+static tc_lcc_status run_edges_on(tc_lcc_graph g, uint64_t* tri, double* lcc, int32_t* edge_src, int32_t* edge_dst,
+                                  uint32_t* edge_tri, hipStream_t st, const EdgeTemps& t, bool allow_rebuild,
+                                  const char* who) {
+    const size_t m = (size_t)g->d.m;
+    tc_lcc_tuning tn;
+    tc_lcc_status s;
+    {
+        std::unique_lock<std::mutex> lk;
+        s = prepare_run(g, st, false, tn, lk, allow_rebuild);
+        if (s != TC_LCC_OK) return s;  // nothing of this call is on the stream yet
+        // from the first launch on, every path waits for the stream before returning
+        k_zero_u32<<<grid_for(std::max<size_t>(m, 64), 256, 8192), 256, 0, st>>>(t.ce, std::max<size_t>(m, 1));
+        k_zero_u32<<<1, 64, 0, st>>>(t.err, 64);
+        if (hipGetLastError() != hipSuccess) {
+            set_error("%s: clearing the counters failed", who);
+            s = TC_LCC_DEVICE_ERROR;
+        }
+        mark(g->d, 6, st);
+        if (s == TC_LCC_OK) s = launch_zero_counts(g, st);
+        mark(g->d, 7, st);
+        if (s == TC_LCC_OK) s = launch_count_edges(g, t.ce, st);
+        mark(g->d, 8, st);
+        if (s == TC_LCC_OK) s = launch_epilogue(g, tri, lcc, st);
+        if (s == TC_LCC_OK && m > 0 && (edge_src || edge_dst || edge_tri)) {
+            const hipError_t e =
+                edge_output(g->d, t.keys, t.alt, t.scratch, t.err, t.rank, t.ce, edge_src, edge_dst, edge_tri, st);
+            if (e != hipSuccess) {
+                set_error("%s: %s", who, hipGetErrorString(e));
+                s = TC_LCC_DEVICE_ERROR;
+            }
+        }
+        mark(g->d, 9, st);
+        if (s == TC_LCC_OK && hipEventRecord(g->last_use, st) != hipSuccess) {
+            set_error("%s: event record failed", who);
+            s = TC_LCC_DEVICE_ERROR;
+        }
+    }
+    unsigned int herr = 0;
+    const hipError_t e1 = s == TC_LCC_OK ? hipMemcpyAsync(&herr, t.err, sizeof(herr), hipMemcpyDeviceToHost, st)
+                                         : hipSuccess;
+    const hipError_t e2 = hipStreamSynchronize(st);
+    if (s != TC_LCC_OK) {
+        (void)hipGetLastError();
+        return s;
+    }
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        set_error("%s: %s", who, hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return TC_LCC_DEVICE_ERROR;
+    }
+    if (herr) {
+        set_error("%s: a radix sort pass gave up waiting for an earlier tile", who);
+        return TC_LCC_DEVICE_ERROR;
+    }
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_run_edges(tc_lcc_graph g, uint64_t* tri, double* lcc, int32_t* edge_src,
+                                          int32_t* edge_dst, uint32_t* edge_tri, void* hip_stream) {
+    tc_lcc_status s = edges_check(g, tri, "tc_lcc_run_edges");
+    if (s != TC_LCC_OK) return s;
+    const size_t m = (size_t)g->d.m, n = (size_t)g->d.n;
+    CallTemps tmp{g->ctx->pool.get(), {}};  // given back after the call has waited for its stream
+    EdgeTemps t;
+    s = tmp.get(std::max<size_t>(m, 1), &t.ce);
+    if (s == TC_LCC_OK) s = tmp.get(std::max<size_t>(m, 1), &t.keys);
+    if (s == TC_LCC_OK) s = tmp.get(std::max<size_t>(m, 1), &t.alt);
+    if (s == TC_LCC_OK) s = tmp.get(radix_sort_scratch_bytes(std::max<size_t>(m, 1)), &t.scratch);
+    if (s == TC_LCC_OK) s = tmp.get(64, &t.err);
+    if (s == TC_LCC_OK) s = tmp.get(std::max<size_t>(n, 1), &t.rank);
+    if (s != TC_LCC_OK) return s;
+    return run_edges_on(g, tri, lcc, edge_src, edge_dst, edge_tri, (hipStream_t)hip_stream, t, true,
+                        "tc_lcc_run_edges");
 }
 
 // ------------------------------------------------------------------ profiling

@@ -549,8 +549,8 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         TCL_HIP(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
     }
 
-    // order: 4-byte-offset graphs first, then 8-byte ones; graphs with vertices beyond the
-    // LDS table (global-memory path) run through the single-graph launches instead
+    // order: 4-byte-offset graphs first, then 8-byte ones; directed graphs and graphs with
+    // vertices beyond the batched LDS slices run through the single-graph launches instead
     std::vector<Plan> plan((size_t)count);
     std::vector<int> ord4, ord8, solo;
     uint32_t need = 0;
@@ -561,7 +561,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         const GraphDev& d = g->d;
         const uint32_t r = region_need(d);
         Plan& p = plan[(size_t)i];
-        if (d.n_global > 0 || d.n_list > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
+        if (d.directed || d.n_global > 0 || d.n_list > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
             p.solo = true;
             solo.push_back(i);
             continue;

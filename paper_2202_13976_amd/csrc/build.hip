@@ -640,6 +640,58 @@ static hipError_t fill(T* p, size_t n, T v, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ direction bits (Eq. 1)
+
+// Directed keys (src << bits | dst); a self-loop gets the all-ones key, dropped by the unique.
+__global__ void k_make_dkeys(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, size_t m_in, int bits,
+                             uint64_t* __restrict__ keys) {
+    const uint64_t loop = (1ull << (2 * bits)) - 1;
+    GRID_STRIDE(i, m_in) {
+        const int32_t a = src[i], b = dst[i];
+        keys[i] = a == b ? loop : (((uint64_t)a << bits) | (uint64_t)b);
+    }
+}
+
+// out-degree of rank r: the length of its id's run of directed keys
+__global__ void k_dout(const int32_t* __restrict__ order, const uint32_t* __restrict__ f,
+                       const uint32_t* __restrict__ l, int64_t n, int32_t* __restrict__ dout_r) {
+    GRID_STRIDE(r, n) {
+        const int32_t v = order[r];
+        dout_r[r] = (int32_t)(l[v] - f[v]);
+    }
+}
+
+__device__ __forceinline__ bool run_has(const uint64_t* __restrict__ k, uint32_t a, uint32_t b, uint64_t key) {
+    const uint32_t end = b;
+    while (a < b) {
+        const uint32_t mid = a + ((b - a) >> 1);
+        if (k[mid] < key) a = mid + 1;
+        else b = mid;
+    }
+    return a < end && k[a] == key;
+}
+
+// Direction bits of oriented edge e = (u -> adj[e]) (u: the row holding e, by a search of
+// out_off): the ids' runs of the sorted, unique directed keys are searched for both directions.
+template <typename OffT>
+__global__ void k_dir(const OffT* __restrict__ out_off, int64_t n, const int32_t* __restrict__ adj, size_t m,
+                      const int32_t* __restrict__ order, const uint64_t* __restrict__ dk,
+                      const uint32_t* __restrict__ f, const uint32_t* __restrict__ l, int bits,
+                      uint8_t* __restrict__ dir) {
+    GRID_STRIDE(e, m) {
+        int64_t lo = 0, hi = n;  // last row r with out_off[r] <= e
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((size_t)out_off[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t x = (uint64_t)order[lo], y = (uint64_t)order[adj[e]];
+        const bool fw = run_has(dk, f[x], l[x], (x << bits) | y);
+        const bool bw = run_has(dk, f[y], l[y], (y << bits) | x);
+        dir[e] = (uint8_t)((fw ? 1u : 0u) | (bw ? 2u : 0u));
+    }
+}
+
 // ------------------------------------------------------------------ host orchestration
 
 namespace {
@@ -690,7 +742,7 @@ hipError_t run_bounds(G g, size_t N, uint32_t* first, uint32_t* last, int64_t n,
 
 template <typename OffT>
 tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
-                          int on_device, int row_max, hipStream_t st, tc_lcc_graph g) {
+                          int on_device, int row_max, bool directed, hipStream_t st, tc_lcc_graph g) {
     GraphDev& d = g->d;
     Temps tmp{ctx->pool.get(), {}};
     const int bits = std::max(1, ceil_log2((uint64_t)n));
@@ -951,20 +1003,63 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
     d.wedges = hs[2];
     d.staged = hs[3];
     d.push_words = hs[4];
+
+    // 6. a directed input (Eq. 1): the skeleton above is its undirected graph; each oriented
+    // edge gets the directions the input held, and each vertex its out-degree
+    if (directed) {
+        TCL_TRY(keep(g, N, &d.dout_r));
+        TCL_TRY(keep(g, std::max<size_t>(m, 1), &d.dir));
+        if (M > 0) {
+            k_make_dkeys<<<grid_for(M, kB, 8192), kB, 0, st>>>(s_dev, d_dev, M, bits, ka);
+            TCL_HIP(hipGetLastError());
+            uint64_t* dsorted = ka;
+            TCL_HIP(radix_sort_u64(ka, kb, M, 0, 2 * bits, sort_scratch, sort_err, st, &dsorted));
+            uint64_t* du = (dsorted == ka) ? kb : ka;
+            const size_t tiles = (M + kScanTile - 1) / kScanTile;
+            uint32_t* toff = pos;
+            k_reduce_tiles<uint32_t, UniqueFlag><<<(unsigned)tiles, kScanThreads, 0, st>>>(
+                UniqueFlag{dsorted, M, (1ull << (2 * bits)) - 1}, M, toff);
+            TCL_HIP(hipGetLastError());
+            TCL_HIP(exclusive_scan<uint32_t>(ArrayIn<uint32_t>{toff, tiles}, tiles + 1, toff, scan32, st));
+            k_unique_tiles<<<(unsigned)tiles, kScanThreads, 0, st>>>(dsorted, M, bits, toff, du, (uint32_t*)kc);
+            TCL_HIP(hipGetLastError());
+            uint32_t md = 0;
+            TCL_HIP(hipMemcpyAsync(&md, toff + tiles, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            TCL_HIP(hipStreamSynchronize(st));
+            TCL_HIP(run_bounds(GroupShift{du, bits}, md, f1, l1, n, st));
+            k_dout<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.order, f1, l1, n, d.dout_r);
+            TCL_HIP(hipGetLastError());
+            if (m > 0) {
+                k_dir<OffT><<<grid_for(m, kB, 16384), kB, 0, st>>>(out_off, n, d.adj, m, d.order, du, f1, l1, bits,
+                                                                  d.dir);
+                TCL_HIP(hipGetLastError());
+            }
+        } else {
+            TCL_HIP(fill<int32_t>(d.dout_r, N, 0, st));
+        }
+        TCL_HIP(hipMemcpyAsync(&serr, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipStreamSynchronize(st));
+        if (serr) {
+            set_error("tc_lcc_build_directed: a radix sort pass gave up waiting for an earlier tile");
+            return TC_LCC_DEVICE_ERROR;
+        }
+        d.directed = true;
+    }
     return TC_LCC_OK;
 }
 
 }  // namespace
 
 tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
-                          int on_device, int offset_bytes, const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g) {
+                          int on_device, int offset_bytes, const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g,
+                          bool directed) {
     // offsets index the m oriented edges; m <= m_in, so 4 bytes suffice when m_in < 2^31
     int ob = offset_bytes;
     if (ob == 0) ob = (m_in < (1ll << 31)) ? 4 : 8;
     g->d.off_bytes = ob;
     const int row_max = tn.row_sort_max > 0 ? std::min(tn.row_sort_max, kRowSortMax) : kRowSortMax;
-    tc_lcc_status s = (ob == 4) ? build_typed<int32_t>(ctx, n, m_in, src, dst, on_device, row_max, st, g)
-                                : build_typed<int64_t>(ctx, n, m_in, src, dst, on_device, row_max, st, g);
+    tc_lcc_status s = (ob == 4) ? build_typed<int32_t>(ctx, n, m_in, src, dst, on_device, row_max, directed, st, g)
+                                : build_typed<int64_t>(ctx, n, m_in, src, dst, on_device, row_max, directed, st, g);
     if (s != TC_LCC_OK) return s;
     s = build_schedule(g, tn, st);
     mark(g->d, 5, st);

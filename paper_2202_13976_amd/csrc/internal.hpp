@@ -101,6 +101,11 @@ struct GraphDev {
     int32_t count_grid = 0, count_lds = 0, count_per_cu = 0;  // last count launch
     int sched_probe = -1;       // probe the schedule was built for
     uint64_t sched_gen = ~0ull; // tuning generation the schedule was built for
+    // directed input (Eq. 1): the lists above are its undirected skeleton
+    bool directed = false;
+    uint8_t* dir = nullptr;     // [m] per oriented edge: bit 0 input held low rank -> high rank,
+                                //     bit 1 high -> low
+    int32_t* dout_r = nullptr;  // [n] out-degree of rank r in the directed input
 };
 
 }  // namespace tcl
@@ -148,7 +153,7 @@ hipError_t radix_counts_clear(void* scratch, hipStream_t st);
 // build.hip
 tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
                           const int32_t* dst, int inputs_on_device, int offset_bytes,
-                          const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g);
+                          const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g, bool directed = false);
 tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
 
 // count.hip
@@ -156,6 +161,15 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
 tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, int spare_per_cu, hipStream_t st);
 tc_lcc_status launch_epilogue(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st);
 tc_lcc_status launch_zero_counts(tc_lcc_graph g, hipStream_t st);
+
+// count_ext.hip: counts that carry more per triangle (see there)
+tc_lcc_status launch_count_edges(tc_lcc_graph g, uint32_t* ce, hipStream_t st);  // ce: [m], zeroed
+tc_lcc_status launch_count_directed(tc_lcc_graph g, hipStream_t st);
+tc_lcc_status launch_epilogue_directed(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t st);
+// per-edge outputs in (lower id, higher id) order from the per-position counts ce; keys and alt
+// hold m words, scratch radix_sort_scratch_bytes(m), rank n entries
+hipError_t edge_output(const GraphDev& d, uint64_t* keys, uint64_t* alt, void* scratch, unsigned int* err,
+                       int32_t* rank, const uint32_t* ce, int32_t* es, int32_t* ed, uint32_t* ec, hipStream_t st);
 
 // batch.hip
 tc_lcc_status batch_engine_create(tc_lcc_ctx ctx);
