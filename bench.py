@@ -94,28 +94,167 @@ def stored_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n, s, d, target_s: float):
-    """The oracle's forward algorithm, single-threaded, on a bounded sample of vertices."""
+def cpu_baseline(n, s, d, target_s: float, samples: int = 3):
+    """The oracle's forward algorithm, single-threaded and pinned to one core, on a bounded
+    sample of vertices: the median rate of `samples` runs of about target_s / samples each."""
+    import numpy as np
     import oracle
     g = oracle.csr(n, s, d)
-    t0 = time.perf_counter()
-    oracle.tc_forward_range(g, 0, 0)  # setup only: orientation of the whole graph
-    setup = time.perf_counter() - t0
-    probe = max(1, n // 2000)
-    t0 = time.perf_counter()
-    _, e1 = oracle.tc_forward_range(g, 0, probe)
-    t1 = time.perf_counter() - t0 - setup
-    frac = min(1.0, max(probe / n, (probe / n) * target_s / max(t1, 1e-3)))
-    hi = max(probe, int(n * frac))
-    t0 = time.perf_counter()
-    _, edges = oracle.tc_forward_range(g, 0, hi)
-    el = time.perf_counter() - t0 - setup
-    return {"value": edges / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+    old_aff = os.sched_getaffinity(0)
+    core = min(old_aff)
+    os.sched_setaffinity(0, {core})  # the calling thread, which runs the oracle
+    try:
+        t0 = time.perf_counter()
+        oracle.tc_forward_range(g, 0, 0)  # setup only: orientation of the whole graph
+        setup = time.perf_counter() - t0
+        probe = max(1, n // 2000)
+        t0 = time.perf_counter()
+        oracle.tc_forward_range(g, 0, probe)
+        t1 = time.perf_counter() - t0 - setup
+        per = target_s / samples
+        frac = min(1.0, max(probe / n, (probe / n) * per / max(t1, 1e-3)))
+        hi = max(probe, int(n * frac))
+        rates, secs = [], []
+        for _ in range(samples):
+            t0 = time.perf_counter()
+            _, edges = oracle.tc_forward_range(g, 0, hi)
+            el = time.perf_counter() - t0 - setup
+            rates.append(edges / el)
+            secs.append(el)
+    finally:
+        os.sched_setaffinity(0, old_aff)
+    k = int(np.argsort(rates)[len(rates) // 2])
+    return {"value": rates[k], "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"forward algorithm (lowest-ranked vertex owns each triangle) over the "
                       f"{hi} vertices with ids in [0, {hi}) of {n} (ids are a random permutation, "
-                      f"so a uniform vertex sample); {edges} oriented edges in {el:.1f} s; "
-                      f"orientation setup ({setup:.1f} s) excluded",
-            "seconds": el}
+                      f"so a uniform vertex sample); {edges} oriented edges per run; median of "
+                      f"{samples} runs ({', '.join(f'{x:.1f}' for x in secs)} s) on one pinned core "
+                      f"(cpu {core}); orientation setup ({setup:.1f} s) excluded",
+            "runs_edges_per_s": rates, "seconds": float(sum(secs))}
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_lines(name):
+    """Per-graph lines stored by tests/golden/make_golden.py from the oracle (m, triangles,
+    sha256(t || LCC)[:16])."""
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)["graphs"]
+
+
+def result_line(m, tri, lcc) -> str:
+    import numpy as np
+    t = tri.cpu().numpy().astype(np.uint64)
+    l = lcc.cpu().numpy()
+    h = hashlib.sha256(t.astype("<u8").tobytes() + l.astype("<f8").tobytes()).hexdigest()[:16]
+    return f"{m} {int(t.sum()) // 3} {h}"
+
+
+def result_lines(torch, ms, tris, lccs):
+    """result_line of many graphs with one device-to-host copy of each kind."""
+    import numpy as np
+    sizes = [t.numel() for t in tris]
+    cut = np.cumsum(sizes)[:-1]
+    ts = np.split(torch.cat([t.reshape(-1) for t in tris]).cpu().numpy().astype(np.uint64), cut)
+    ls = np.split(torch.cat([x.reshape(-1) for x in lccs]).cpu().numpy(), cut)
+    out = []
+    for m, t, l in zip(ms, ts, ls):
+        h = hashlib.sha256(t.astype("<u8").tobytes() + l.astype("<f8").tobytes()).hexdigest()[:16]
+        out.append(f"{m} {int(t.sum()) // 3} {h}")
+    return out
+
+
+def hbm_copy_rate(torch, pkg, nbytes: int = 2 << 30, reps: int = 10):
+    """Achievable HBM bandwidth: the library's streaming copy kernel (tc_lcc_hbm_copy) over
+    nbytes, timed with HIP events on its stream; read + written bytes over the median time."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        pkg.hbm_copy(a, b, st)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        pkg.hbm_copy(a, b, st)
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ok = bool(torch.equal(a, b))
+    del a, b
+    med = float(np.median(ts))
+    return {"kernel": "k_hbm_copy (16-byte nontemporal loads and stores)", "bytes_read": nbytes,
+            "bytes_written": nbytes, "median_ms": med, "gbs": 2 * nbytes / (med * 1e-3) / 1e9, "copy_correct": ok}
+
+
+def build_bytes(info, raw_pairs: int) -> int:
+    """Least HBM bytes of one build: the raw pairs read once (8 B per pair) and the graph
+    written once (its device bytes).  The sorts move far more; this is the floor."""
+    return 8 * int(raw_pairs) + int(info.device_bytes)
+
+
+def ext_bench(ctx, torch, pkg, n, src, dst, offset_bytes, triangles: int, reps: int = 5):
+    """The two extensions of the count on the same workload, each timed on HIP events of its
+    stream (the graph's phase timings): per-edge triangle counts (tc_lcc_run_edges) and the
+    clustering coefficient of Eq. 1 with the raw pairs taken as directed edges (as drawn)."""
+    import numpy as np
+    out = {}
+    ctx.set_profiling(True)
+    g = ctx.build_csr(n, src, dst, offset_bytes=offset_bytes)
+    info = g.info()
+    g.run_edges()
+    cnt, rest, wall = [], [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        tri, lcc, es, ed, ec = g.run_edges()
+        wall.append(time.perf_counter() - t0)
+        tm = g.timings()
+        cnt.append(tm.run_count_ms)
+        rest.append(tm.run_epilogue_ms)
+    sum_c = int(ec.to(torch.int64).sum())
+    sum_t = int(tri.sum())
+    g.free()
+    del es, ed, ec
+    # bytes of the extended count: the plain count's, plus one read-modify-write of a 4-byte
+    # counter per triangle (its tail entry), per kept in-edge (its tail's hits) and per staged
+    # entry (the flush), and the clearing of the m counters
+    w = int(info.offset_bytes)
+    eb = count_bytes(info) + 8 * triangles + 8 * int(info.kept_in_edges) + 8 * int(info.staged_entries) + 4 * int(info.m)
+    c_ms = float(np.median(cnt))
+    out["edges"] = {"entry": "tc_lcc_run_edges", "m": int(info.m), "count_ms": c_ms,
+                    "epilogue_and_edge_output_ms": float(np.median(rest)), "call_ms": float(np.median(wall)) * 1e3,
+                    "teps": int(info.m) / (float(np.median(wall))), "alg_bytes_per_launch": eb,
+                    "roofline_frac": eb / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "sum_edge_counts_equals_sum_t": sum_c == sum_t}
+    gd = ctx.build_directed(n, src, dst, offset_bytes=offset_bytes)
+    bt = gd.timings().as_dict()
+    infod = gd.info()
+    num = torch.empty(n, dtype=torch.int64, device=src.device)
+    cl = torch.empty(n, dtype=torch.float64, device=src.device)
+    gd.run(num, cl)
+    dc = []
+    for _ in range(reps):
+        gd.run(num, cl)
+        dc.append(gd.timings().run_count_ms)
+    torch.cuda.synchronize()
+    gd.free()
+    # directed: the plain count's bytes plus the direction byte of every hit's two list entries,
+    # of every kept in-edge and of every staged entry
+    db = count_bytes(infod) + 2 * triangles + int(infod.kept_in_edges) + int(infod.staged_entries)
+    d_ms = float(np.median(dc))
+    out["directed"] = {"entry": "tc_lcc_build_directed + tc_lcc_run (Eq. 1)", "directed_pairs": int(src.numel()),
+                       "skeleton_m": int(infod.m), "build_ms": sum(v for k, v in bt.items() if k.startswith("build")),
+                       "count_ms": d_ms, "teps": int(infod.m) / (d_ms * 1e-3), "alg_bytes_per_launch": db,
+                       "roofline_frac": db / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "sum_numerator": int(num.sum())}
+    ctx.set_profiling(False)
+    return out
 
 
 def batch_bench(ctx, torch, log_fn, reps: int = 3):
@@ -124,7 +263,7 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
     import synth
     specs = synth.batch_specs()
     dev = torch.device("cuda", 0)
-    graphs, tris, lccs = [], [], []
+    graphs, tris, lccs, ms = [], [], [], []
     m_total = 0
     wedges = 0
     alg_bytes = 0
@@ -134,6 +273,7 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
         g = ctx.build_csr(n, torch.from_numpy(s).to(dev), torch.from_numpy(d).to(dev), offset_bytes=4)
         graphs.append(g)
         info = g.info()
+        ms.append(int(info.m))
         m_total += int(info.m)
         wedges += int(info.wedges)
         alg_bytes += count_bytes(info)
@@ -161,6 +301,8 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
         batched()
         t_batch.append(time.perf_counter() - t0)
     same = all(torch.equal(a, b) for a, b in zip(tris, loop_tris))
+    ref = golden_lines("batch4096_seed7")
+    oracle_ok = None if ref is None else result_lines(torch, ms, tris, lccs) == ref
     tl, tb = float(np.median(t_loop)), float(np.median(t_batch))
     # the autotuner on the batched launch's knobs, then the same measurement again
     log_fn("[bench] autotuning the batched launch")
@@ -185,6 +327,7 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
             "graphs": len(specs), "m_total": m_total, "wedges": wedges, "alg_bytes": alg_bytes,
             "per_graph_ms": tl * 1e3, "batched_ms": tb * 1e3, "speedup": tl / tb,
             "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same),
+            "matches_oracle_digests": oracle_ok,
             "autotuned": {"batch_grab": tuned.batch_grab, "batch_heavy_bits": tuned.batch_heavy_bits,
                           "batched_ms": tt * 1e3, "speedup": tl / tt, "tuning_seconds": tune_s,
                           "results_identical": bool(same_tuned)}}
@@ -307,6 +450,16 @@ def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: 
     plain = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=1)
     sat = run(plain, 0.0)
     plain.close()
+    torch.cuda.synchronize()
+    # every graph of the pool was requested at least once by now (2000 picks of 64): the plain
+    # path's outputs are the reference for the batched runs, and are checked against the oracle
+    seen = sorted(set(int(k) for k in picks_all))
+    ref_outs = {k: (outs[k][0].clone(), outs[k][1].clone()) for k in seen}
+    gold = golden_lines("serving64_seed9")
+    plain_oracle_ok = None
+    if gold is not None:
+        plain_oracle_ok = result_lines(torch, [ms[k] for k in seen], [ref_outs[k][0] for k in seen],
+                                       [ref_outs[k][1] for k in seen]) == [gold[k] for k in seen]
     t_edges = sum(ms[k] for k in picks_all[n_warm:])
     sat_rate = n_req * sat["teps"] / t_edges  # requests per second when the plain path is saturated
     rate = load * sat_rate
@@ -329,6 +482,12 @@ def serve_bench(ctx, torch, log_fn, n_req: int = 2000, n_warm: int = 200, load: 
                              "batched": run(batched, r, sweep_req, sweep_warm)})
     plain.close()
     batched.close()
+    torch.cuda.synchronize()
+    # the last runs were the batched server's: every request's outputs overwrite their graph's
+    res["results_identical"] = all(torch.equal(outs[k][0], ref_outs[k][0]) and
+                                   torch.equal(outs[k][1], ref_outs[k][1]) for k in seen)
+    res["matches_oracle_digests"] = plain_oracle_ok
+    res["graphs_checked"] = len(seen)
     for g in graphs:
         g.free()
     return res
@@ -345,8 +504,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
     ap.add_argument("--no-strategies", action="store_true", help="skip the per-probe-strategy count times")
+    ap.add_argument("--no-ext", action="store_true", help="skip the per-edge and directed legs")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="after timing, copy 1 GiB with an elementwise kernel 3 times (reference for HBM counters)")
+                    help="after timing, copy 1 GiB with the library's streaming copy kernel 3 times "
+                         "(reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the path runs on a "
@@ -400,6 +561,11 @@ def main():
     ctx.set_profiling(False)
     log("[bench] tc_lcc_run on the resident graph")
     run_res = run_timing(ctx, torch, n, src, dst, w["offset_bytes"], tri, lcc)
+    triangles = int(tri.sum()) // 3
+    log("[bench] streaming copy (achievable HBM bandwidth)")
+    copy = hbm_copy_rate(torch, pkg)
+    build_ms = sum(v for k, v in phases.items() if k.startswith("build"))
+    bb = build_bytes(info, len(s))
 
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
@@ -411,9 +577,19 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_count (intersection + scatter)", "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": count_ms},
+                     "avg_launch_ms": count_ms,
+                     "achievable_gbs": copy["gbs"], "frac_of_achievable": achieved / copy["gbs"],
+                     "dram_frac": (traffic / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "full_list_alg_frac": full_list_bytes(info) / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "full_list_note": "the whole-list streaming figure 4W + (4+2w)m + (2w+16)n prices work "
+                                       "(every head's full N+ per oriented edge) that the wedge-pull kernel "
+                                       "does not do; above 1 here, so it is not a fraction of anything"},
+        "build_roofline": {"bound": "hbm", "least_bytes": bb, "ms": build_ms,
+                           "achieved": bb / (build_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": bb / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                           "bytes_note": "8 B per raw pair read + the built graph's device bytes written"},
+        "hbm_copy": copy,
         "run_only_teps": m / (run_ms * 1e-3),
-        "full_list_alg_frac": full_list_bytes(info) / (count_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phases_ms": phases,
         "run_resident": run_res,
         "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
@@ -421,8 +597,12 @@ def main():
                   "staged_entries": int(info.staged_entries), "max_out_degree": int(info.max_out_degree),
                   "max_degree": int(info.max_degree), "device_bytes": int(info.device_bytes),
                   "count_grid": int(info.count_grid), "count_lds_bytes": int(info.count_lds_bytes),
-                  "count_blocks_per_cu": int(info.count_blocks_per_cu), "table_slots": int(info.table_slots)},
+                  "count_blocks_per_cu": int(info.count_blocks_per_cu), "table_slots": int(info.table_slots),
+                  "triangles": triangles},
     }
+    if not args.no_ext:
+        log("[bench] per-edge counts and directed Eq. 1 on the same workload")
+        out["ext"] = ext_bench(ctx, torch, pkg, n, src, dst, w["offset_bytes"], triangles)
     if not args.no_strategies:
         log("[bench] probe strategies on the resident graph")
         ctx.set_profiling(True)
@@ -435,18 +615,18 @@ def main():
         out["serve"] = serve_bench(ctx, torch, log)
     ctx.close()
     if args.calibrate_copy:
-        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a plain copy through the
-        # shader cores; copy_ itself may use the DMA engines, which the counters do not see)
-        a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        # the library's streaming copy (tc_lcc_hbm_copy): reads 1 GiB and writes 1 GiB through the
+        # shader cores (copy_ itself may use the DMA engines, which the counters do not see)
+        a = torch.ones(1 << 28, dtype=torch.int32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            torch.mul(a, 1, out=b)
+            pkg.hbm_copy(a, b)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = a.numel() * 4
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cb = cpu_baseline(n, s, d, args.cpu_seconds)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "runs_edges_per_s")}
         out["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(out), flush=True)
 
