@@ -32,12 +32,16 @@
 
 namespace tcl {
 
-constexpr int kLightGrab = 8;  // light vertices a wave takes per queue access (large graphs)
+constexpr int kLightGrab = 8;       // light vertices a wave takes per queue access (large graphs)
+constexpr int kLightGrabLarge = 16;  // ... and for the largest graphs
 
-// Light vertices per grab: kLightGrab when there are plenty per wave, single ones when few
-// (so that a small graph spreads its light vertices over all waves).
+// Light vertices per grab: 16 when there are at least four grabs of 16 per wave, 8 when there
+// are four of 8, single ones when few (so that a small graph spreads its light vertices over
+// all waves, and a mid-size one still takes several per queue access).
 __host__ __device__ __forceinline__ int light_grab(int64_t n_light, int64_t waves) {
-    return n_light >= waves * (int64_t)kLightGrab * 4 ? kLightGrab : 1;
+    return n_light >= waves * (int64_t)kLightGrabLarge * 4 ? kLightGrabLarge
+           : n_light >= waves * (int64_t)kLightGrab * 4    ? kLightGrab
+                                                           : 1;
 }
 
 template <typename OffT, int PROBE>
