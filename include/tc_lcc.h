@@ -199,15 +199,21 @@ tc_lcc_status tc_lcc_batch_progress(tc_lcc_ctx ctx, tc_lcc_ticket t, int count, 
 /* ------------------------------------------------------------------ serving */
 
 /* A request server over device-resident graphs with continuous batching.
- * A dispatcher thread admits submitted requests in arrival order while the scratch of
- * the requests in flight (8 bytes per vertex of each request's graph) stays within
+ * A dispatcher thread admits submitted requests in arrival order while their scratch fits
  * hbm_budget_bytes (0 = no cap), gathers everything admitted at once into one batched
  * launch, and starts it as soon as fewer than max_inflight batches are running; so
  * requests that arrive while others run are batched together and overlap with them.
- * Each request completes, and returns its budget share, as soon as its own graph is
- * done (tc_lcc_batch_progress), not when its whole batch is.
+ * The budget is device memory actually held: a batching server with a budget takes, when
+ * it is created, one zeroed arena of the budget rounded down to 8 bytes (and the context's
+ * batch descriptors for max_batch graphs), and allocates nothing while it serves.
+ * A batched request takes its graph's counters (8 bytes per vertex) first-fit
+ * from the arena and returns them, zeroed again by the epilogue, as soon as its own graph
+ * is done (tc_lcc_batch_progress), not when its whole batch is; a request whose graph takes
+ * the single-graph launches (directed, or lists beyond a block's hash) uses the graph's own
+ * counters.  OVER_BUDGET from create if the arena cannot be had within the context's budget.
  * max_inflight = max_batch = 1 gives the plain path: one request at a time through
- * tc_lcc_run.  Results are identical to tc_lcc_run's for every request. */
+ * tc_lcc_run (its budget then bounds 8 bytes per vertex of the request in flight).  Results
+ * are identical to tc_lcc_run's for every request. */
 typedef struct tc_lcc_server_s* tc_lcc_server;
 
 typedef struct {
@@ -223,7 +229,8 @@ tc_lcc_status tc_lcc_server_create(tc_lcc_ctx ctx, uint64_t hbm_budget_bytes, in
 
 /* Enqueue one request: graph g (built in the server's context), outputs tri/lcc as in
  * tc_lcc_run (device pointers, kept alive until the request is polled complete).
- * Returns at once with *request_id.  OVER_BUDGET if the request alone exceeds the budget. */
+ * Returns at once with *request_id.  OVER_BUDGET if the request alone exceeds the budget
+ * (the arena's size, for a batching server). */
 tc_lcc_status tc_lcc_server_submit(tc_lcc_server s, tc_lcc_graph g, uint64_t* tri, double* lcc,
                                    uint64_t* request_id);
 

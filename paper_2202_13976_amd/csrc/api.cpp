@@ -100,6 +100,50 @@ tc_lcc_status Pool::alloc(size_t bytes, void** out) {
     return TC_LCC_OK;
 }
 
+tc_lcc_status Pool::alloc_exact(size_t bytes, void** out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    if (fail_after_ >= 0 && fail_after_-- == 0) {
+        set_error("device allocation of %zu bytes refused (failure injection)", bytes);
+        return TC_LCC_OUT_OF_MEMORY;
+    }
+    if (budget_ && in_use_ + bytes > budget_) {
+        set_error("device budget of %llu bytes exceeded (%llu in use, %zu requested)",
+                  (unsigned long long)budget_, (unsigned long long)in_use_, bytes);
+        return TC_LCC_OVER_BUDGET;
+    }
+    if (budget_ && in_use_ + pooled_ + bytes > budget_) {
+        for (auto& kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        pooled_ = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        for (auto& kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        pooled_ = 0;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of %zu bytes failed", bytes);
+            return TC_LCC_OUT_OF_MEMORY;
+        }
+    }
+    in_use_ += bytes;
+    live_[p] = bytes;
+    *out = p;
+    return TC_LCC_OK;
+}
+
+void Pool::free_exact(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    in_use_ -= it->second;
+    live_.erase(it);
+    (void)hipFree(p);
+}
+
 void Pool::release(void* p) {
     if (!p) return;
     std::lock_guard<std::mutex> lk(mu_);

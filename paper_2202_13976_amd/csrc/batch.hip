@@ -113,6 +113,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
                                                                int which) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int64_t s_item;
+    __shared__ uint32_t s_tcnt[kBatchThreads];  // per wave: hits of the 64 tails of a chunk
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t rb = h->region;
     const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
@@ -129,8 +130,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
         const CountArgs<OffT> a = batch_args<OffT>(G);
         const int32_t v = G.vlist[item - G.heavy_base];
         unsigned long long local = 0;
-        process_vertex<OffT, TC_LCC_PROBE_AUTO, kBatchThreads / kWave>(a, v, lds, rb * (kBatchThreads / kWave),
-                                                                        threadIdx.x, w, local);
+        process_vertex<OffT, TC_LCC_PROBE_AUTO, kBatchThreads / kWave, true>(a, v, lds, rb * (kBatchThreads / kWave),
+                                                                              threadIdx.x, w, local);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
         if (grid >= hhi - hlo) break;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
             const VertexHead<OffT> hd{__builtin_amdgcn_readlane(hv, q), lane_value(hb0, q), lane_value(hb1, q),
                                       lane_value(hi0, q), lane_value(hi1, q)};
             unsigned long long local = 0;
-            process_vertex<OffT, TC_LCC_PROBE_AUTO, 1>(a, hd, region, rb, lane, 0, local);
+            process_vertex<OffT, TC_LCC_PROBE_AUTO, 1, true>(a, hd, region, rb, lane, 0, local, s_tcnt + w * kWave);
             const unsigned long long ws = wave_sum(local);
             if (lane == 0 && ws) atomicAdd(&G.t[hd.v], ws);
         }
@@ -378,9 +379,9 @@ uint32_t region_need(const GraphDev& d) {
     return std::min(bm, hs);
 }
 
-// LDS bytes per wave of the batched launch.  Graphs that need more (id ranges or out-lists
-// too large for a wave's slice) have heavy vertices that one wave would count for a long
-// time; they take the single-graph launches, which give such vertices a whole block.
+// LDS bytes per wave of the batched launch: the smallest class that every batched graph's
+// largest table fits, capped at the largest class.  Vertices whose tables do not fit (id
+// ranges or out-lists too large for a slice) are searched in HBM by their wave or block.
 constexpr uint32_t kRegionClasses[] = {2048, 4096};
 constexpr int kNumRegionClasses = (int)(sizeof(kRegionClasses) / sizeof(kRegionClasses[0]));
 
@@ -505,8 +506,29 @@ struct Plan {
 
 }  // namespace
 
-extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs,
-                                             uint64_t* const* tri, double* const* lcc, tc_lcc_ticket* out) {
+bool tcl::batch_graph_solo(tc_lcc_graph g) {
+    std::lock_guard<std::mutex> gl(g->mu);
+    return g->d.directed || g->d.n_global > 0 || g->d.n_list > 0;
+}
+
+tc_lcc_status tcl::batch_reserve(tc_lcc_ctx ctx, size_t graphs) {
+    TCL_HIP(hipSetDevice(ctx->device));
+    Engine* e = engine(ctx);
+    std::lock_guard<std::mutex> lk(e->mu);
+    for (Slot& s : e->slots) {
+        if (s.busy) continue;
+        if (!s.stream) {
+            TCL_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+            TCL_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+        }
+        tc_lcc_status st = ensure_capacity(ctx, s, std::max<size_t>(graphs, 1), std::max<size_t>(graphs, 1), 1);
+        if (st != TC_LCC_OK) return st;
+    }
+    return TC_LCC_OK;
+}
+
+tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs, uint64_t* const* tri,
+                                     double* const* lcc, unsigned long long* const* scratch, tc_lcc_ticket* out) {
     if (!ctx || count <= 0 || !graphs || !tri || !out) {
         set_error("tc_lcc_batch_submit: null argument or count <= 0");
         return TC_LCC_INVALID_ARGUMENT;
@@ -549,19 +571,21 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         TCL_HIP(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
     }
 
-    // order: 4-byte-offset graphs first, then 8-byte ones; directed graphs and graphs with
-    // vertices beyond the batched LDS slices run through the single-graph launches instead
+    // order: 4-byte-offset graphs first, then 8-byte ones; directed graphs and graphs with lists
+    // longer than the single-graph launch's hash (which that launch takes as a sorted list in
+    // its larger table) run through the single-graph launches instead.  Vertices of batched
+    // graphs whose tables do not fit their slice are searched in HBM inside the batch.
     std::vector<Plan> plan((size_t)count);
     std::vector<int> ord4, ord8, solo;
     uint32_t need = 0;
-    size_t scratch = 0;
+    size_t need_scratch = 0;
     for (int i = 0; i < count; ++i) {
         tc_lcc_graph g = graphs[i];
         std::lock_guard<std::mutex> gl(g->mu);
         const GraphDev& d = g->d;
         const uint32_t r = region_need(d);
         Plan& p = plan[(size_t)i];
-        if (d.directed || d.n_global > 0 || d.n_list > 0 || r > kRegionClasses[kNumRegionClasses - 1]) {
+        if (d.directed || d.n_global > 0 || d.n_list > 0) {
             p.solo = true;
             solo.push_back(i);
             continue;
@@ -571,8 +595,8 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
         for (int c = 0; c <= 40 - heavy_bits && c < 48; ++c) big += d.class_count[c];
         p.heavy = big;
         p.light = d.n_block - big + d.n_wave;
-        need = std::max(need, r);
-        scratch += (size_t)d.n;
+        need = std::max(need, std::min(r, kRegionClasses[kNumRegionClasses - 1]));
+        need_scratch += (size_t)d.n;
         (d.off_bytes == 4 ? ord4 : ord8).push_back(i);
     }
     uint32_t region = kRegionClasses[kNumRegionClasses - 1];
@@ -585,8 +609,9 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     // the earliest done flags come as soon as possible
     std::stable_sort(solo.begin(), solo.end(), [&](int a, int b) { return graphs[a]->d.wedges < graphs[b]->d.wedges; });
     const int nb = (int)(ord4.size() + ord8.size());
-    tc_lcc_status st =
-        ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), (size_t)count, std::max<size_t>(scratch, 1));
+    // with counters given by the caller (each graph's own, all zero) the slot's are not used
+    tc_lcc_status st = ensure_capacity(ctx, *s, (size_t)std::max(nb, 1), (size_t)count,
+                                       scratch ? 1 : std::max<size_t>(need_scratch, 1));
     if (st != TC_LCC_OK) return st;
 
     // reserve the slot before anything is launched on it: from here on the graphs count as
@@ -624,7 +649,7 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
             b.vlist = d.vlist;
             b.order = d.order;
             b.deg_r = d.deg_r;
-            b.t = s->d_scratch + soff;
+            b.t = scratch ? scratch[i] : s->d_scratch + soff;
             b.tri = (unsigned long long*)tri[i];
             b.lcc = lcc ? lcc[i] : nullptr;
             b.n = d.n;
@@ -689,6 +714,11 @@ extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc
     }
     *out = s->ticket;
     return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs,
+                                             uint64_t* const* tri, double* const* lcc, tc_lcc_ticket* out) {
+    return batch_submit_with(ctx, count, graphs, tri, lcc, nullptr, out);
 }
 
 extern "C" tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int* graphs_done) {

@@ -461,6 +461,79 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
     }
 }
 
+// One wave over the tails of v's in-edges with windows that cross tail boundaries: for graphs
+// whose tails are short (the many-small-graphs batch: a dozen candidates per tail), a window of
+// one tail would leave most of the 64 lanes idle.  Per chunk of 64 in-edges, lane k holds
+// in-edge k; the tails are laid end to end (exclusive prefix sums of their lengths) and every
+// window takes the next 64 candidates of that sequence.  Lane i finds the tail of its candidate
+// by a binary search over the lanes' prefix sums (lane shuffles), reads the candidate, probes
+// it, and counts a hit at its entry of N+(v) and in its tail's LDS counter (tcnt: 64 words of
+// this wave); the tails' counts go to t(u) once the chunk is done.
+template <typename OffT, int MODE>
+__device__ void walk_flat(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb, uint32_t* tcnt,
+                          unsigned long long& local) {
+    const int lane = lane_id();
+    const OffT i0 = ie.i0, i1 = ie.i1;
+    int32_t u = ie.u, len = ie.len;
+    OffT st = ie.st;
+    for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
+        if (cb != i0) {
+            const OffT k = cb + (OffT)lane;
+            u = 0;
+            st = 0;
+            len = 0;
+            if (k < i1) {
+                u = a.in_u[k];
+                st = a.in_start[k];
+                len = a.in_len[k];
+            }
+        }
+        const int32_t incl = wave_inclusive_scan(len);
+        const int32_t excl = incl - len;
+        const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+        tcnt[lane] = 0u;
+        wave_lds_sync();
+        for (int32_t base = 0; base < total; base += kWave) {
+            const int32_t c = base + lane;
+            const bool valid = c < total;
+            // last tail k whose first candidate is at or before c (tails are nonempty)
+            int k = 0;
+#pragma unroll
+            for (int step = kWave / 2; step >= 1; step >>= 1) {
+                const int probe = k + step;
+                const int32_t e = __shfl(excl, probe < kWave ? probe : kWave - 1, kWave);
+                if (probe < kWave && e <= c) k = probe;
+            }
+            const int32_t ek = __shfl(excl, k, kWave);
+            OffT sk;
+            if constexpr (sizeof(OffT) == 8) {
+                const uint64_t s64 = (uint64_t)st;
+                sk = (OffT)((uint64_t)(uint32_t)__shfl((int32_t)(uint32_t)s64, k, kWave) |
+                            ((uint64_t)(uint32_t)__shfl((int32_t)(uint32_t)(s64 >> 32), k, kWave) << 32));
+            } else {
+                sk = (OffT)__shfl((int32_t)st, k, kWave);
+            }
+            const int32_t x = a.adj[sk + (OffT)(valid ? c - ek : 0)];
+            bool hit;
+            if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
+                const uint32_t ii = (uint32_t)(x - tb.base);  // candidates are ranks above v
+                const uint32_t wi = min(ii >> 5, tb.words);   // beyond the range: the zero guard word
+                const uint2 e = *reinterpret_cast<const uint2*>(tb.bm + 2 * wi);
+                hit = valid && __builtin_amdgcn_ubfe(e.x, ii, 1u) != 0u;
+                if (hit) atomicAdd(&tb.cnt[e.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(e.x, 0u, ii))], 1u);
+            } else {
+                hit = probe_one<MODE>(tb, x, valid);
+            }
+            if (hit) atomicAdd(&tcnt[k], 1u);
+            local += hit ? 1ull : 0ull;
+        }
+        wave_lds_sync();
+        const uint32_t mine = tcnt[lane];
+        if (mine) atomicAdd(&a.t[u], (unsigned long long)mine);
+        wave_lds_sync();
+    }
+}
+
 // Bytes of the bitmap layout for `words` bitmap words (plus the guard word), dv counters and
 // one spare word per lane.
 __host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
@@ -483,9 +556,15 @@ __device__ __forceinline__ VertexHead<OffT> vertex_head(const CountArgs<OffT>& a
     return VertexHead<OffT>{v, a.out_off[v], a.out_off[v + 1], a.in_off[v], a.in_off[v + 1]};
 }
 
-template <typename OffT, int PROBE, int NWAVES>
+// FALLBACK (the batched kernel): a vertex whose bucket hash does not fit the region either is
+// searched in N+(v) where it lies in HBM (each hit added to t(w) at once), so a graph whose
+// largest lists exceed a batched slice still runs in the batch.
+// tcnt (the batched kernel's light vertices, NWAVES == 1): 64 LDS words of this wave; the bitmap
+// and hash probes then take windows across tail boundaries (walk_flat).
+template <typename OffT, int PROBE, int NWAVES, bool FALLBACK = false>
 __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>& hd, uint8_t* region,
-                               uint32_t region_bytes, int gtid, int wig, unsigned long long& local) {
+                               uint32_t region_bytes, int gtid, int wig, unsigned long long& local,
+                               uint32_t* tcnt = nullptr) {
     constexpr int gsize = NWAVES * kWave;
     const int32_t v = hd.v;
     const OffT b0 = hd.b0;
@@ -503,6 +582,21 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
         tb.words = (tb.span + 31u) >> 5;
         mode = (PROBE != TC_LCC_PROBE_HASH && bitmap_bytes(tb.words, dv) <= region_bytes) ? TC_LCC_PROBE_BITMAP
                                                                                            : TC_LCC_PROBE_HASH;
+        if constexpr (FALLBACK) {
+            if (mode == TC_LCC_PROBE_HASH && 8u * (uint32_t)hash_table_slots(dv) > region_bytes) {
+                mode = kProbeGlobal;
+                tb.keys = const_cast<int32_t*>(nv);
+                tb.T = dv;
+                tb.tg = a.t;
+            }
+        }
+    }
+    if constexpr (FALLBACK) {
+        if (mode == kProbeGlobal) {
+            walk_tails<OffT, kProbeGlobal, NWAVES>(a, ie, tb, wig, local);
+            group_sync<NWAVES>();
+            return;
+        }
     }
 
     // ---- stage N+(v)
@@ -544,7 +638,12 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
     group_sync<NWAVES>();
 
     // ---- probe the tails of the in-edges
-    if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, wig, local);
+    if (NWAVES == 1 && FALLBACK && tcnt && (mode == TC_LCC_PROBE_BITMAP || mode == TC_LCC_PROBE_HASH)) {
+        if constexpr (NWAVES == 1 && FALLBACK) {
+            if (mode == TC_LCC_PROBE_BITMAP) walk_flat<OffT, TC_LCC_PROBE_BITMAP>(a, ie, tb, tcnt, local);
+            else walk_flat<OffT, TC_LCC_PROBE_HASH>(a, ie, tb, tcnt, local);
+        }
+    } else if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, wig, local);
     else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, wig, local);
     else if (mode == TC_LCC_PROBE_MERGE) walk_tails_hybrid<OffT, NWAVES>(a, v, tb, wig, local);
     else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, ie, tb, wig, local);
@@ -568,10 +667,10 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
     group_sync<NWAVES>();
 }
 
-template <typename OffT, int PROBE, int NWAVES>
+template <typename OffT, int PROBE, int NWAVES, bool FALLBACK = false>
 __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region,
                                                uint32_t region_bytes, int gtid, int wig, unsigned long long& local) {
-    process_vertex<OffT, PROBE, NWAVES>(a, vertex_head(a, v), region, region_bytes, gtid, wig, local);
+    process_vertex<OffT, PROBE, NWAVES, FALLBACK>(a, vertex_head(a, v), region, region_bytes, gtid, wig, local);
 }
 
 }  // namespace tcl

@@ -54,6 +54,10 @@ class Pool {
     static size_t round(size_t bytes);
     // failure injection: the next `after` allocations succeed, the one after fails (< 0: off)
     void fail_after(int64_t after);
+    // a block of exactly `bytes` (no size class), counted in use until free_exact, which gives
+    // it back to HIP at once instead of caching it
+    tc_lcc_status alloc_exact(size_t bytes, void** out);
+    void free_exact(void* p);
 
    private:
     int device_;
@@ -178,6 +182,17 @@ void batch_engine_destroy(tc_lcc_ctx ctx);
 std::mutex& batch_mutex(tc_lcc_ctx ctx);
 // make st wait for every batch in flight that holds g (caller holds batch_mutex)
 tc_lcc_status batch_fence_graph(tc_lcc_ctx ctx, tc_lcc_graph g, hipStream_t st);
+// the submission of tc_lcc_batch_submit; scratch (may be null): per graph, zeroed counters of
+// n entries the batch uses instead of the slot's own (graphs that take the single-graph
+// launches ignore theirs); they are zero again once the graph's done flag is up
+tc_lcc_status batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs, uint64_t* const* tri,
+                                double* const* lcc, unsigned long long* const* scratch, tc_lcc_ticket* out);
+// whether a batch runs g through the single-graph launches (directed, or lists longer than a
+// block's hash)
+bool batch_graph_solo(tc_lcc_graph g);
+// grow every idle slot's descriptors and flags to `graphs` entries now, so that later
+// submissions of up to that many graphs with caller-given counters allocate nothing
+tc_lcc_status batch_reserve(tc_lcc_ctx ctx, size_t graphs);
 
 // api.cpp: the single-graph run of tc_lcc_run, with launch_count's spare_per_cu;
 // engine_locked: the caller holds batch_mutex (tc_lcc_batch_submit)

@@ -1,11 +1,18 @@
 // Serving loop: continuous batching of triangle-count / LCC requests on device-resident graphs.
 //
 // Requests (graph, output buffers) arrive at any time through submit().  A dispatcher
-// thread admits them in arrival order while the device footprint of the requests in
-// flight stays within the server's HBM budget (a request needs the scratch counters of
-// its graph, 8 bytes per vertex), groups everything admitted at once into one batch of
-// the persistent batched launch, and starts it as soon as one of the in-flight slots is
-// free.  Requests that arrive while earlier batches run join the next batch and overlap
+// thread admits them in arrival order while their scratch fits the server's HBM budget,
+// groups everything admitted at once into one batch of the persistent batched launch, and
+// starts it as soon as one of the in-flight slots is free.
+//
+// The budget is memory actually held: with batching and a budget, the server takes one
+// device arena of that size (rounded down to 8 bytes) when it is created (and the batch engine's descriptors
+// for max_batch graphs), and nothing more while it serves.  A batched request needs its
+// graph's counters, 8 bytes per vertex, carved first-fit from the arena at admission; they
+// return to the arena when the request's graph is done, which is also when the epilogue has
+// set them back to zero, so the next request finds them clean.  Requests for graphs that
+// take the single-graph launches use their graph's own counters and need no arena space.
+// Requests that arrive while earlier batches run join the next batch and overlap
 // with them on the GPU.  Completion is observed per request from the per-graph done
 // flags of its batch, so a small graph batched with a large one leaves as soon as it is
 // counted; every request records its arrival, admission and completion times (steady
@@ -14,6 +21,7 @@
 // plain one-graph-per-launch path, for comparison.
 #include <chrono>
 #include <cstring>
+#include <iterator>
 
 #include "internal.hpp"
 
@@ -30,7 +38,8 @@ struct Request {
     tc_lcc_graph g = nullptr;
     uint64_t* tri = nullptr;
     double* lcc = nullptr;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0;       // budget share: arena bytes (batching), or 8 B per vertex (plain path)
+    uint64_t arena_off = ~0ull;  // its counters in the arena while it runs
     int64_t t_arrive = 0, t_admit = 0, t_done = 0;
     int batch_size = 0;
     tc_lcc_status status = TC_LCC_OK;
@@ -62,6 +71,9 @@ struct tc_lcc_server_s {
     std::vector<tcl::Flight> flights;
     uint64_t inflight_bytes = 0;
     uint64_t next_id = 1;
+    // batching with a budget: the counters of running requests, first-fit in one device block
+    uint8_t* arena = nullptr;
+    std::map<uint64_t, uint64_t> free_ranges;  // offset -> bytes, coalesced
     bool stop = false;
     hipStream_t stream = nullptr;  // plain path
     std::thread worker;
@@ -71,15 +83,60 @@ struct tc_lcc_server_s {
 namespace tcl {
 namespace {
 
-// Completes one request of flight f: its budget share is returned and pollers wake up.
+constexpr uint64_t kArenaAlign = 8;  // the counters are 8-byte words
+
+uint64_t arena_need(const tc_lcc_graph g) {
+    return (8ull * (uint64_t)g->d.n + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+// First fit of `bytes` in the arena's free ranges; ~0 if none is large enough.
+uint64_t arena_take(tc_lcc_server s, uint64_t bytes) {
+    for (auto it = s->free_ranges.begin(); it != s->free_ranges.end(); ++it) {
+        if (it->second < bytes) continue;
+        const uint64_t off = it->first, rest = it->second - bytes;
+        s->free_ranges.erase(it);
+        if (rest) s->free_ranges[off + bytes] = rest;
+        return off;
+    }
+    return ~0ull;
+}
+
+void arena_give(tc_lcc_server s, uint64_t off, uint64_t bytes) {
+    auto next = s->free_ranges.lower_bound(off);
+    if (next != s->free_ranges.end() && off + bytes == next->first) {  // join the range after
+        bytes += next->second;
+        next = s->free_ranges.erase(next);
+    }
+    if (next != s->free_ranges.begin()) {  // join the range before
+        auto prev = std::prev(next);
+        if (prev->first + prev->second == off) {
+            prev->second += bytes;
+            return;
+        }
+    }
+    s->free_ranges[off] = bytes;
+}
+
+// Completes one request of flight f: its budget share (its arena range, whose counters the
+// epilogue has set back to zero by the time its done flag is seen) is returned and pollers
+// wake up.
 void retire(tc_lcc_server s, Flight& f, Request* r, int64_t t, tc_lcc_status st) {
     r->t_done = t;
     r->status = st;
     r->done = true;
     r->g->inflight--;
     s->inflight_bytes -= r->bytes;
+    if (r->arena_off != ~0ull) {
+        arena_give(s, r->arena_off, r->bytes);
+        r->arena_off = ~0ull;
+    }
     f.open--;
     s->cv_done.notify_all();
+}
+
+__global__ void k_arena_clear(unsigned long long* __restrict__ p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
 }
 
 void worker_loop(tc_lcc_server s) {
@@ -126,7 +183,15 @@ void worker_loop(tc_lcc_server s) {
             Flight f;
             while (!s->pending.empty() && (int)f.reqs.size() < s->max_batch) {
                 Request* r = s->pending.front();
-                if (s->budget && s->inflight_bytes + f.bytes + r->bytes > s->budget) break;
+                if (s->arena) {
+                    if (r->bytes) {
+                        const uint64_t off = arena_take(s, r->bytes);
+                        if (off == ~0ull) break;  // the head waits for counters to free up
+                        r->arena_off = off;
+                    }
+                } else if (s->budget && s->inflight_bytes + f.bytes + r->bytes > s->budget) {
+                    break;
+                }
                 s->pending.pop_front();
                 f.reqs.push_back(r);
                 f.bytes += r->bytes;
@@ -136,6 +201,7 @@ void worker_loop(tc_lcc_server s) {
             std::vector<tc_lcc_graph> gs;
             std::vector<uint64_t*> ts;
             std::vector<double*> ls;
+            std::vector<unsigned long long*> cs;
             for (Request* r : f.reqs) {
                 r->t_admit = t;
                 r->batch_size = (int)f.reqs.size();
@@ -143,10 +209,12 @@ void worker_loop(tc_lcc_server s) {
                 gs.push_back(r->g);
                 ts.push_back(r->tri);
                 ls.push_back(r->lcc);
+                cs.push_back(r->arena_off != ~0ull ? (unsigned long long*)(s->arena + r->arena_off) : nullptr);
             }
             tc_lcc_status st;
             if (s->batching) {
-                st = tc_lcc_batch_submit(s->ctx, (int)gs.size(), gs.data(), ts.data(), ls.data(), &f.ticket);
+                st = batch_submit_with(s->ctx, (int)gs.size(), gs.data(), ts.data(), ls.data(),
+                                       s->arena ? cs.data() : nullptr, &f.ticket);
             } else {
                 st = tc_lcc_run(gs[0], ts[0], ls[0], s->stream);
                 if (st == TC_LCC_OK &&
@@ -162,6 +230,10 @@ void worker_loop(tc_lcc_server s) {
                     r->done = true;
                     r->t_done = now_ns();
                     r->g->inflight--;
+                    if (r->arena_off != ~0ull) {  // nothing ran: the counters are still zero
+                        arena_give(s, r->arena_off, r->bytes);
+                        r->arena_off = ~0ull;
+                    }
                 }
                 s->cv_done.notify_all();
                 continue;
@@ -208,6 +280,36 @@ extern "C" tc_lcc_status tc_lcc_server_create(tc_lcc_ctx ctx, uint64_t hbm_budge
         set_error("tc_lcc_server_create: stream creation failed");
         return TC_LCC_DEVICE_ERROR;
     }
+    if (s->batching && hbm_budget_bytes > 0) {
+        // all the device memory the server will hold, taken now: the counters' arena, and the
+        // batch engine's descriptors for max_batch graphs
+        const uint64_t ab = hbm_budget_bytes / kArenaAlign * kArenaAlign;
+        void* p = nullptr;
+        tc_lcc_status st = ab ? ctx->pool->alloc_exact(ab, &p) : TC_LCC_OVER_BUDGET;
+        if (st == TC_LCC_OK) {
+            hipStream_t cs = nullptr;
+            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+                st = TC_LCC_DEVICE_ERROR;
+            } else {
+                k_arena_clear<<<(unsigned)std::min<uint64_t>((ab / 8 + 255) / 256, 4096), 256, 0, cs>>>(
+                    (unsigned long long*)p, ab / 8);
+                if (hipGetLastError() != hipSuccess || hipStreamSynchronize(cs) != hipSuccess) st = TC_LCC_DEVICE_ERROR;
+                (void)hipStreamDestroy(cs);
+            }
+            if (st == TC_LCC_OK) st = batch_reserve(ctx, (size_t)std::min(max_batch, 1 << 16));
+        }
+        if (st != TC_LCC_OK) {
+            (void)hipGetLastError();
+            if (p) ctx->pool->free_exact(p);
+            delete s;
+            set_error("tc_lcc_server_create: the arena of the budget (%llu bytes) could not be set up",
+                      (unsigned long long)hbm_budget_bytes);
+            return st == TC_LCC_DEVICE_ERROR ? TC_LCC_DEVICE_ERROR : TC_LCC_OVER_BUDGET;
+        }
+        s->arena = (uint8_t*)p;
+        s->free_ranges[0] = ab;
+        s->budget = ab;
+    }
     s->worker = std::thread(worker_loop, s);
     *out = s;
     return TC_LCC_OK;
@@ -224,11 +326,13 @@ extern "C" tc_lcc_status tc_lcc_server_submit(tc_lcc_server s, tc_lcc_graph g, u
     r->g = g;
     r->tri = tri;
     r->lcc = lcc;
-    r->bytes = 8ull * (uint64_t)g->d.n;
+    if (s->arena) r->bytes = batch_graph_solo(g) ? 0 : arena_need(g);
+    else r->bytes = 8ull * (uint64_t)g->d.n;
     if (s->budget && r->bytes > s->budget) {
+        const unsigned long long need = r->bytes;
         delete r;
-        set_error("tc_lcc_server_submit: request needs %llu bytes, budget is %llu",
-                  (unsigned long long)(8ull * (uint64_t)g->d.n), (unsigned long long)s->budget);
+        set_error("tc_lcc_server_submit: request needs %llu bytes, budget is %llu", need,
+                  (unsigned long long)s->budget);
         return TC_LCC_OVER_BUDGET;
     }
     r->t_arrive = now_ns();
@@ -292,6 +396,7 @@ extern "C" tc_lcc_status tc_lcc_server_destroy(tc_lcc_server s) {
     if (s->worker.joinable()) s->worker.join();
     for (auto& kv : s->reqs) delete kv.second;
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->arena) s->ctx->pool->free_exact(s->arena);  // every batch has finished (the worker drained them)
     delete s;
     return TC_LCC_OK;
 }

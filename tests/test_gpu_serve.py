@@ -3,6 +3,7 @@ results of each graph counted alone."""
 import hashlib
 import json
 import os
+import threading
 import time
 
 import numpy as np
@@ -119,6 +120,44 @@ def test_tiny_budget_queues(ctx, pool):
     # no launch ever held more than the budget
     for inf, sz in zip(infos, sizes):
         assert inf.batch_size * min(sizes) <= budget + 1 or inf.batch_size == 1
+
+
+def test_budget_is_device_memory_held(ctx, pool):
+    """A batching server with a budget takes its counters' arena when it is created and
+    allocates nothing while it serves: the context's device memory, sampled all through a
+    stream, never moves from its value right after the server's creation; what the server added
+    is its budget plus the batch descriptors reserved for max_batch graphs.  The budget holds the
+    counters of three of the largest graphs, so requests wait for arena space, and every result
+    equals the graph counted alone."""
+    print("[gpu] server budget = memory held", flush=True)
+    graphs, alone = pool
+    in0, _ = ctx.memory()
+    nmax = max(g.n for g in graphs)
+    budget = 3 * 8 * nmax
+    server = pkg.Server(ctx, budget_bytes=budget, max_inflight=4, max_batch=1024)
+    in1, _ = ctx.memory()
+    descriptors = 4 * (1 << 20) + 4 * 4096  # four slots' descriptors for 1024 graphs, pool-rounded
+    assert budget - 8 <= in1 - in0 <= budget + descriptors
+    samples = []
+    stop = threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            samples.append(ctx.memory()[0])
+            time.sleep(0.0002)
+
+    th = threading.Thread(target=sampler)
+    th.start()
+    rng = np.random.default_rng(17)
+    picks = rng.integers(0, len(graphs), 300)
+    outs, infos = drive(server, graphs, picks, rng.exponential(0.0001, 300))
+    stop.set()
+    th.join()
+    server.close()
+    check(outs, alone)
+    assert samples and min(samples) == in1 and max(samples) == in1, (min(samples), max(samples), in1)
+    assert ctx.memory()[0] == in0 + (in1 - in0 - budget // 8 * 8), "the arena is given back on destroy"
+    assert max(inf.batch_size for inf in infos) > 1
 
 
 def test_over_budget_and_unknown(ctx, pool):
