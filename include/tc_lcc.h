@@ -177,7 +177,9 @@ tc_lcc_status tc_lcc_run_edges(tc_lcc_graph g, uint64_t* tri, double* lcc, int32
  * Work items over (graph, vertex tile) are taken from a device queue by a grid
  * sized to the GPU; the launch is recorded once in a HIP graph and replayed.
  * *out receives a ticket for batch_poll.  Results equal tc_lcc_run's for
- * every graph.  Graphs and outputs must stay alive until the ticket is done. */
+ * every graph.  Graphs and outputs must stay alive until the ticket is done.  A batch runs on
+ * the library's own streams, not ordered after the caller's: any work of the caller that
+ * writes or reads the output buffers must be complete before the submission. */
 tc_lcc_status tc_lcc_batch_submit(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs,
                                   uint64_t* const* tri, double* const* lcc, tc_lcc_ticket* out);
 
@@ -230,7 +232,8 @@ tc_lcc_status tc_lcc_server_create(tc_lcc_ctx ctx, uint64_t hbm_budget_bytes, in
 /* Enqueue one request: graph g (built in the server's context), outputs tri/lcc as in
  * tc_lcc_run (device pointers, kept alive until the request is polled complete).
  * Returns at once with *request_id.  OVER_BUDGET if the request alone exceeds the budget
- * (the arena's size, for a batching server). */
+ * (the arena's size, for a batching server).  The request runs on the library's own streams,
+ * not ordered after the caller's: any work of the caller on tri/lcc must be complete first. */
 tc_lcc_status tc_lcc_server_submit(tc_lcc_server s, tc_lcc_graph g, uint64_t* tri, double* lcc,
                                    uint64_t* request_id);
 

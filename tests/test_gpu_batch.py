@@ -36,6 +36,8 @@ def build(ctx, n, s, d, ob):
 def outputs(graphs):
     tris = [torch.full((g.n,), -1, dtype=torch.int64, device="cuda") for g in graphs]
     lccs = [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for g in graphs]
+    # batches run on the library's streams: the fills must be done before the submission
+    torch.cuda.current_stream().synchronize()
     return tris, lccs
 
 

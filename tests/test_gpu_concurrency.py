@@ -73,8 +73,11 @@ def same_as_ref(tri, lcc, ref):
 
 
 def outputs(graphs):
-    return ([torch.full((g.n,), -1, dtype=torch.int64, device="cuda") for g in graphs],
-            [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for g in graphs])
+    out = ([torch.full((g.n,), -1, dtype=torch.int64, device="cuda") for g in graphs],
+           [torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda") for g in graphs])
+    # batches run on the library's streams: the fills must be done before the submission
+    torch.cuda.current_stream().synchronize()
+    return out
 
 
 def test_threads_submit_batches_with_solo_graphs(ctx, mixed):

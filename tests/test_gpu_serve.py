@@ -51,6 +51,8 @@ def drive(server, graphs, picks, gaps):
         g = graphs[k]
         tri = torch.full((g.n,), -1, dtype=torch.int64, device="cuda")
         lcc = torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda")
+        # the server runs on the library's streams: the fills above must be done first
+        torch.cuda.current_stream().synchronize()
         outs.append((k, tri, lcc))
         ids.append(server.submit(g, tri, lcc))
     infos = [server.poll(i, block=True) for i in ids]
@@ -90,12 +92,14 @@ def test_burst_is_batched(ctx, pool):
     torch.cuda.synchronize()
     server = pkg.Server(ctx, budget_bytes=0, max_inflight=1, max_batch=4096)
     tri_b = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    torch.cuda.current_stream().synchronize()
     first = server.submit(big, tri_b)
     outs, ids = [], []
     for k in list(range(len(graphs))) * 2:
         g = graphs[k]
         tri = torch.full((g.n,), -1, dtype=torch.int64, device="cuda")
         lcc = torch.full((g.n,), -1.0, dtype=torch.float64, device="cuda")
+        torch.cuda.current_stream().synchronize()
         outs.append((k, tri, lcc))
         ids.append(server.submit(g, tri, lcc))
     server.poll(first, block=True)
