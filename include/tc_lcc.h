@@ -170,6 +170,24 @@ tc_lcc_status tc_lcc_run(tc_lcc_graph g, uint64_t* tri, double* lcc, void* hip_s
 tc_lcc_status tc_lcc_run_edges(tc_lcc_graph g, uint64_t* tri, double* lcc, int32_t* edge_src, int32_t* edge_dst,
                                uint32_t* edge_tri, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): tc_lcc_run_edges with every temporary in a static
+ * device buffer of TC_LCC_NOALLOC_BYTES that the library holds on each GPU it runs on until
+ * the process ends.  The call allocates nothing (no hipMalloc, no pool block, no host buffer).
+ * Arguments, outputs and results are those of tc_lcc_run_edges.  Limits and behaviour:
+ *   - the temporaries need 20 bytes per undirected edge, 4 per vertex and the sort's tile
+ *     counts (about 2 KiB per 16384 edges), each part rounded to 256 bytes; a graph that needs
+ *     more than TC_LCC_NOALLOC_BYTES gets INVALID_ARGUMENT, before any device work;
+ *   - the graph's schedule is used as it stands: a tuning change since the graph's last run is
+ *     not applied (applying it would allocate); results never depend on it;
+ *   - every call on one GPU uses that GPU's one buffer, and each call clears what it needs,
+ *     so results never depend on an earlier call; calls that overlap on one GPU (other
+ *     threads, other streams) race on the buffer and must be serialised by the caller;
+ *   - synchronous: the call waits for hip_stream before it returns. */
+#define TC_LCC_NOALLOC_BYTES (64ull << 20)
+tc_lcc_status tc_lcc_run_edges_noalloc(tc_lcc_graph g, uint64_t* tri, double* lcc, int32_t* edge_src,
+                                       int32_t* edge_dst, uint32_t* edge_tri, void* hip_stream);
+
 /* ------------------------------------------------------------------ batches */
 
 /* Count many graphs in one persistent launch.  graphs[i] (built in ctx) writes

@@ -73,7 +73,7 @@ class RequestInfo(ctypes.Structure):
 _lib = None
 EXPORTS = [
     "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_debug_fail_alloc", "tc_lcc_build_csr",
-    "tc_lcc_build_directed", "tc_lcc_run_edges", "tc_lcc_graph_info",
+    "tc_lcc_build_directed", "tc_lcc_run_edges", "tc_lcc_run_edges_noalloc", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
     "tc_lcc_batch_progress", "tc_lcc_autotune", "tc_lcc_tuning_load",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
@@ -99,6 +99,7 @@ def lib():
     L.tc_lcc_build_csr.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
     L.tc_lcc_build_directed.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
     L.tc_lcc_run_edges.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.tc_lcc_run_edges_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tc_lcc_graph_info.argtypes = [vp, ctypes.POINTER(GraphStats)]
     L.tc_lcc_graph_export.argtypes = [vp, vp, vp, vp, vp]
     L.tc_lcc_graph_free.argtypes = [vp]

@@ -213,8 +213,11 @@ extern "C" tc_lcc_status tc_lcc_ctx_create(int device, uint64_t hbm_budget_bytes
     c->tuning = default_tuning();
     c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     c->lds_per_block = prop.sharedMemPerBlock;
-    const tc_lcc_status bs = batch_engine_create(c);
+    tc_lcc_status bs = batch_engine_create(c);
+    uint8_t* nb = nullptr;
+    if (bs == TC_LCC_OK) bs = noalloc_base(device, &nb);  // this device's copy of the static scratch
     if (bs != TC_LCC_OK) {
+        batch_engine_destroy(c);
         delete c;
         return bs;
     }
@@ -630,6 +633,71 @@ extern "C" tc_lcc_status tc_lcc_run_edges(tc_lcc_graph g, uint64_t* tri, double*
     if (s != TC_LCC_OK) return s;
     return run_edges_on(g, tri, lcc, edge_src, edge_dst, edge_tri, (hipStream_t)hip_stream, t, true,
                         "tc_lcc_run_edges");
+}
+
+// ------------------------------------------------------------------ per-edge run without allocation
+
+// Every temporary of tc_lcc_run_edges_noalloc: one copy on each GPU the library runs on, held
+// until the process ends.  In host code this name is not a device address; the address of
+// each GPU's copy comes from hipGetSymbolAddress (noalloc_base) and only that is used.
+static __device__ __align__(256) uint8_t scratch[TC_LCC_NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+std::unordered_map<int, uint8_t*> g_noalloc_base;  // device -> its copy of `scratch`
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// The address of the current device's copy of the static buffer, looked up once per device
+// (with that device current) and kept.
+tc_lcc_status tcl::noalloc_base(int device, uint8_t** out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_base.find(device);
+    if (it == g_noalloc_base.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            set_error("static scratch of device %d: hipGetSymbolAddress failed: %s", device, hipGetErrorString(e));
+            return TC_LCC_DEVICE_ERROR;
+        }
+        it = g_noalloc_base.emplace(device, (uint8_t*)p).first;
+    }
+    *out = it->second;
+    return TC_LCC_OK;
+}
+
+extern "C" tc_lcc_status tc_lcc_run_edges_noalloc(tc_lcc_graph g, uint64_t* tri, double* lcc, int32_t* edge_src,
+                                                  int32_t* edge_dst, uint32_t* edge_tri, void* hip_stream) {
+    tc_lcc_status s = edges_check(g, tri, "tc_lcc_run_edges_noalloc");
+    if (s != TC_LCC_OK) return s;
+    const size_t m = std::max<size_t>((size_t)g->d.m, 1), n = std::max<size_t>((size_t)g->d.n, 1);
+    // layout of the buffer: counters, keys, alternate keys, sort scratch, error word, ranks
+    const size_t o_ce = 0, o_keys = o_ce + up256(4 * m), o_alt = o_keys + up256(8 * m);
+    const size_t o_rs = o_alt + up256(8 * m), o_err = o_rs + up256(radix_sort_scratch_bytes(m));
+    const size_t o_rank = o_err + 256, need = o_rank + up256(4 * n);
+    if (need > (size_t)TC_LCC_NOALLOC_BYTES) {
+        set_error("tc_lcc_run_edges_noalloc: the graph needs %zu bytes of temporaries (%zu edges, %zu vertices), "
+                  "beyond the static buffer of %llu bytes",
+                  need, (size_t)g->d.m, (size_t)g->d.n, (unsigned long long)TC_LCC_NOALLOC_BYTES);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    TCL_HIP(hipSetDevice(g->ctx->device));
+    uint8_t* base = nullptr;
+    s = noalloc_base(g->ctx->device, &base);
+    if (s != TC_LCC_OK) return s;
+    EdgeTemps t;
+    t.ce = (uint32_t*)(base + o_ce);
+    t.keys = (uint64_t*)(base + o_keys);
+    t.alt = (uint64_t*)(base + o_alt);
+    t.scratch = base + o_rs;
+    t.err = (unsigned int*)(base + o_err);
+    t.rank = (int32_t*)(base + o_rank);
+    return run_edges_on(g, tri, lcc, edge_src, edge_dst, edge_tri, (hipStream_t)hip_stream, t, false,
+                        "tc_lcc_run_edges_noalloc");
 }
 
 // ------------------------------------------------------------------ profiling

@@ -202,4 +202,8 @@ tc_lcc_status run_graph(tc_lcc_graph g, uint64_t* tri, double* lcc, hipStream_t 
 // tuning defaults
 tc_lcc_tuning default_tuning();
 
+// api.cpp: the address of `device`'s copy of the static scratch of tc_lcc_run_edges_noalloc
+// (looked up with that device current, once, and kept)
+tc_lcc_status noalloc_base(int device, uint8_t** out);
+
 }  // namespace tcl
