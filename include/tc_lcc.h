@@ -111,7 +111,7 @@ typedef struct {
     uint64_t push_words;      /* sum over oriented edges (u -> v) of |N+(v)| (whole-list streaming) */
     int64_t global_vertices;  /* active vertices whose N+(v) exceeds the LDS table (searched in HBM) */
     int32_t directed;         /* 1: built by tc_lcc_build_directed (m, max_degree: its undirected skeleton) */
-    int32_t reserved_;        /* 0 */
+    int32_t compact;          /* 1: built by tc_lcc_build_streamed (compact reverse lists) */
 } tc_lcc_graph_stats;
 
 tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);
@@ -128,6 +128,40 @@ tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* out);
 tc_lcc_status tc_lcc_build_directed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
                                     const int32_t* dst, int inputs_on_device, int offset_bytes,
                                     void* hip_stream, tc_lcc_graph* out);
+
+/* Pair source of tc_lcc_build_streamed.  Writes pairs [first, first + count) of the input's
+ * sequence of m_in pairs into src[0, count) and dst[0, count): device buffers of the library,
+ * valid during the call.  Device work that writes them must be enqueued on hip_stream (or be
+ * finished when the source returns).  The same (first, count) must give the same pairs on every
+ * call.  Returns 0 on success; any other value ends the build with INVALID_ARGUMENT. */
+typedef int (*tc_lcc_pair_source)(void* user, uint64_t first, uint64_t count, int32_t* src, int32_t* dst,
+                                  void* hip_stream);
+
+/* Build the graph of tc_lcc_build_csr from more raw pairs than device memory holds beside the
+ * build (R-MAT scale 30 of Table II: 1.7e10 pairs, 137 GB as int32).  The pairs are pulled from
+ * `source` in chunks of chunk_pairs (0: a default of 2^28), in several passes over the whole
+ * sequence:
+ *   1. a histogram of the pairs' lower ends splits the id range into partitions of about
+ *      partition_pairs pairs each (0: all in one);
+ *   2. one pass per partition keeps the pairs whose lower end lies in it, and sorts and
+ *      deduplicates them on the GPU into the partition's rows of the upper lists (lower id to
+ *      higher ids);
+ *   3. the lists are ranked, oriented and sorted as by tc_lcc_build_csr, and the reverse lists
+ *      are built in a compact form: u and a 16-bit position per in-edge.
+ * The graph is the simple undirected graph the pairs describe (Sec. II-A), with the orientation,
+ * ranks and sorted lists of tc_lcc_build_csr (Sec. II-B), so tc_lcc_run's results are the same.
+ * Offsets are 8 bytes wide.  Peak device memory is about 14 bytes per pair in flight plus the
+ * graph (about 13 bytes per undirected edge and 25 per vertex).
+ * The in-edges of a vertex are not in rank order in this form; tc_lcc_run_edges refuses such a
+ * graph (UNSUPPORTED) and a batch gives it the single-graph launches.
+ * Errors: INVALID_ARGUMENT for n outside [1, 2^31-1], a null source, an id outside [0, n), a
+ *   source that fails or gives more pairs in a partition on a later pass than the histogram
+ *   counted; UNSUPPORTED when an oriented list is longer than 65537 entries or a partition holds
+ *   2^32 pairs or more; OUT_OF_MEMORY / OVER_BUDGET as tc_lcc_build_csr.
+ * Synchronous: waits for hip_stream before it returns. */
+tc_lcc_status tc_lcc_build_streamed(tc_lcc_ctx ctx, int64_t n, uint64_t m_in, tc_lcc_pair_source source, void* user,
+                                    uint64_t chunk_pairs, uint64_t partition_pairs, void* hip_stream,
+                                    tc_lcc_graph* out);
 
 /* Copy the built structure to host memory (for checking the builder).  Every
  * pointer may be NULL to skip that array.

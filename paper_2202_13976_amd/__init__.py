@@ -42,7 +42,7 @@ class GraphStats(ctypes.Structure):
                 ("count_grid", ctypes.c_int32), ("count_lds_bytes", ctypes.c_int32),
                 ("count_blocks_per_cu", ctypes.c_int32), ("table_slots", ctypes.c_int32),
                 ("push_words", ctypes.c_uint64), ("global_vertices", ctypes.c_int64),
-                ("directed", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("directed", ctypes.c_int32), ("compact", ctypes.c_int32)]
 
 
 class Timings(ctypes.Structure):
@@ -73,13 +73,18 @@ class RequestInfo(ctypes.Structure):
 _lib = None
 EXPORTS = [
     "tc_lcc_ctx_create", "tc_lcc_ctx_destroy", "tc_lcc_ctx_memory", "tc_lcc_debug_fail_alloc", "tc_lcc_build_csr",
-    "tc_lcc_build_directed", "tc_lcc_run_edges", "tc_lcc_run_edges_noalloc", "tc_lcc_graph_info",
+    "tc_lcc_build_directed", "tc_lcc_build_streamed", "tc_lcc_run_edges", "tc_lcc_run_edges_noalloc", "tc_lcc_graph_info",
     "tc_lcc_graph_export", "tc_lcc_graph_free", "tc_lcc_run", "tc_lcc_batch_submit", "tc_lcc_batch_poll",
     "tc_lcc_batch_progress", "tc_lcc_autotune", "tc_lcc_tuning_load",
     "tc_lcc_get_tuning", "tc_lcc_set_tuning", "tc_lcc_set_profiling", "tc_lcc_graph_timings",
     "tc_lcc_server_create", "tc_lcc_server_submit", "tc_lcc_server_poll", "tc_lcc_server_destroy",
     "tc_lcc_hbm_copy", "tc_lcc_status_string", "tc_lcc_last_error",
 ]
+
+
+# tc_lcc_pair_source: (user, first, count, src, dst, hip_stream) -> 0 on success
+PAIR_SOURCE = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p)
 
 
 def lib():
@@ -98,6 +103,7 @@ def lib():
     L.tc_lcc_debug_fail_alloc.argtypes = [vp, i64]
     L.tc_lcc_build_csr.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
     L.tc_lcc_build_directed.argtypes = [vp, i64, i64, vp, vp, i32, i32, vp, ctypes.POINTER(vp)]
+    L.tc_lcc_build_streamed.argtypes = [vp, i64, u64, PAIR_SOURCE, vp, u64, u64, vp, ctypes.POINTER(vp)]
     L.tc_lcc_run_edges.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tc_lcc_run_edges_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tc_lcc_graph_info.argtypes = [vp, ctypes.POINTER(GraphStats)]
@@ -259,6 +265,31 @@ class Context:
         """Directed input (tc_lcc_build_directed): src[e] -> dst[e]; Graph.run then gives the
         numerator and the clustering coefficient of Eq. 1.  Same argument forms as build_csr."""
         return self.build_csr(n, src, dst, offset_bytes=offset_bytes, stream=stream, _entry="tc_lcc_build_directed")
+
+    def build_streamed(self, n: int, m_in: int, source, chunk_pairs: int = 0, partition_pairs: int = 0,
+                       stream=None) -> Graph:
+        """tc_lcc_build_streamed: pairs pulled from `source(first, count, src_ptr, dst_ptr, stream_ptr)`,
+        which writes pairs [first, first + count) into the two device buffers (int addresses) with
+        work on the given HIP stream, the same pairs on every call.  An exception in the source
+        ends the build with INVALID_ARGUMENT and is raised again here."""
+        errors = []
+
+        def cb(_user, first, count, sp, dp, stp):
+            try:
+                source(int(first), int(count), int(sp or 0), int(dp or 0), int(stp or 0))
+                return 0
+            except Exception as e:  # noqa: BLE001 - re-raised below
+                errors.append(e)
+                return 1
+
+        fn = PAIR_SOURCE(cb)
+        h = ctypes.c_void_p()
+        status = lib().tc_lcc_build_streamed(self.handle, n, m_in, fn, None, chunk_pairs, partition_pairs,
+                                             _stream_ptr(stream), ctypes.byref(h))
+        if errors:
+            raise errors[0]
+        _check(status, "tc_lcc_build_streamed")
+        return Graph(self, h)
 
     def tuning(self) -> Tuning:
         t = Tuning()

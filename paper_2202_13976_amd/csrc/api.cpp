@@ -303,19 +303,10 @@ static void graph_release(tc_lcc_graph g) {
     delete g;
 }
 
-static tc_lcc_status build_common(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
-                                  int inputs_on_device, int offset_bytes, void* hip_stream, tc_lcc_graph* out,
-                                  bool directed) {
-    if (!ctx || !out) {
-        set_error("tc_lcc_build_csr: null context or out");
-        return TC_LCC_INVALID_ARGUMENT;
-    }
-    if (n < 1 || n > 2147483647ll || m_in < 0 || m_in >= (1ll << 32) || (m_in > 0 && (!src || !dst)) ||
-        (offset_bytes != 0 && offset_bytes != 4 && offset_bytes != 8)) {
-        set_error("tc_lcc_build_csr: bad size, pointer or offset width (n=%lld m_in=%lld offset_bytes=%d)",
-                  (long long)n, (long long)m_in, offset_bytes);
-        return TC_LCC_INVALID_ARGUMENT;
-    }
+// A new graph built by `build(tuning, stream, graph)`, with its profiling events and last-use
+// event; on failure the graph's memory is returned once the stream is idle.
+template <typename Build>
+static tc_lcc_status build_with(tc_lcc_ctx ctx, void* hip_stream, tc_lcc_graph* out, Build&& build) {
     TCL_HIP(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)hip_stream;
     tc_lcc_graph g = new (std::nothrow) tc_lcc_graph_s();
@@ -339,7 +330,7 @@ static tc_lcc_status build_common(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const
         tn = ctx->tuning;
         gen = ctx->tuning_gen;
     }
-    tc_lcc_status s = build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, tn, st, g, directed);
+    tc_lcc_status s = build(tn, st, g);
     if (s == TC_LCC_OK) {
         g->d.sched_gen = gen;
         if (hipEventCreateWithFlags(&g->last_use, hipEventDisableTiming) != hipSuccess ||
@@ -358,6 +349,50 @@ static tc_lcc_status build_common(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const
     ctx->graphs++;
     *out = g;
     return TC_LCC_OK;
+}
+
+static tc_lcc_status build_common(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src, const int32_t* dst,
+                                  int inputs_on_device, int offset_bytes, void* hip_stream, tc_lcc_graph* out,
+                                  bool directed) {
+    if (!ctx || !out) {
+        set_error("tc_lcc_build_csr: null context or out");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (n < 1 || n > 2147483647ll || m_in < 0 || m_in >= (1ll << 32) || (m_in > 0 && (!src || !dst)) ||
+        (offset_bytes != 0 && offset_bytes != 4 && offset_bytes != 8)) {
+        set_error("tc_lcc_build_csr: bad size, pointer or offset width (n=%lld m_in=%lld offset_bytes=%d)",
+                  (long long)n, (long long)m_in, offset_bytes);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    return build_with(ctx, hip_stream, out, [&](const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g) {
+        return build_graph(ctx, n, m_in, src, dst, inputs_on_device, offset_bytes, tn, st, g, directed);
+    });
+}
+
+extern "C" tc_lcc_status tc_lcc_build_streamed(tc_lcc_ctx ctx, int64_t n, uint64_t m_in, tc_lcc_pair_source source,
+                                               void* user, uint64_t chunk_pairs, uint64_t partition_pairs,
+                                               void* hip_stream, tc_lcc_graph* out) {
+    if (!ctx || !out || !source) {
+        set_error("tc_lcc_build_streamed: null context, source or out");
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    if (n < 1 || n > 2147483647ll) {
+        set_error("tc_lcc_build_streamed: n=%lld outside [1, 2^31-1]", (long long)n);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    const uint64_t chunk = chunk_pairs ? chunk_pairs : (1ull << 28);
+    StreamSource src = [&](uint64_t first, uint64_t count, int32_t* s, int32_t* d, hipStream_t st) {
+        const int rc = source(user, first, count, s, d, (void*)st);
+        if (rc != 0) {
+            set_error("tc_lcc_build_streamed: the pair source returned %d for pairs [%llu, %llu)", rc,
+                      (unsigned long long)first, (unsigned long long)(first + count));
+            return TC_LCC_INVALID_ARGUMENT;
+        }
+        return TC_LCC_OK;
+    };
+    return build_with(ctx, hip_stream, out, [&](const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g) {
+        return build_streamed(ctx, n, m_in, src, chunk, partition_pairs, tn, st, g);
+    });
 }
 
 extern "C" tc_lcc_status tc_lcc_build_csr(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t* src,
@@ -395,7 +430,7 @@ extern "C" tc_lcc_status tc_lcc_graph_info(tc_lcc_graph g, tc_lcc_graph_stats* o
     out->push_words = g->d.push_words;
     out->global_vertices = g->d.n_global;
     out->directed = g->d.directed ? 1 : 0;
-    out->reserved_ = 0;
+    out->compact = g->d.compact ? 1 : 0;
     return TC_LCC_OK;
 }
 
@@ -555,6 +590,10 @@ static tc_lcc_status edges_check(tc_lcc_graph g, uint64_t* tri, const char* who)
     }
     if (g->d.directed) {
         set_error("%s: per-edge counts are defined here for undirected graphs", who);
+        return TC_LCC_UNSUPPORTED;
+    }
+    if (g->d.compact) {
+        set_error("%s: not available for a graph with compact reverse lists (tc_lcc_build_streamed)", who);
         return TC_LCC_UNSUPPORTED;
     }
     return TC_LCC_OK;

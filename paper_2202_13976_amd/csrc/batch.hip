@@ -74,6 +74,7 @@ __device__ __forceinline__ CountArgs<OffT> batch_args(const BatchGraph& G) {
     a.in_u = G.in_u;
     a.in_start = (const OffT*)G.in_start;
     a.in_len = G.in_len;
+    a.in_pos = nullptr;
     a.vlist = G.vlist;
     a.n_block = a.n_wave = a.n_global = 0;
     a.t = G.t;
@@ -508,7 +509,7 @@ struct Plan {
 
 bool tcl::batch_graph_solo(tc_lcc_graph g) {
     std::lock_guard<std::mutex> gl(g->mu);
-    return g->d.directed || g->d.n_global > 0 || g->d.n_list > 0;
+    return g->d.directed || g->d.compact || g->d.n_global > 0 || g->d.n_list > 0;
 }
 
 tc_lcc_status tcl::batch_reserve(tc_lcc_ctx ctx, size_t graphs) {
@@ -585,7 +586,7 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
         const GraphDev& d = g->d;
         const uint32_t r = region_need(d);
         Plan& p = plan[(size_t)i];
-        if (d.directed || d.n_global > 0 || d.n_list > 0) {
+        if (d.directed || d.compact || d.n_global > 0 || d.n_list > 0) {
             p.solo = true;
             solo.push_back(i);
             continue;

@@ -1180,4 +1180,684 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     return TC_LCC_OK;
 }
 
+
+// ------------------------------------------------------------------ streamed build
+//
+// A graph whose raw pairs do not fit HBM beside the build (R-MAT scale 30: 1.7e10 pairs, 137 GB
+// as int32) is built from a pair source the library calls for consecutive chunks, once per
+// pass.  The passes:
+//   0. a histogram of the pairs' lower ends (top 12 bits) sets partitions of the id range that
+//      each hold at most `partition_pairs` pairs;
+//   1. per partition: the canonical keys of its pairs (lower end in the partition) are
+//      gathered, sorted and made unique; the higher ends are appended to the upper lists of
+//      the canonical CSR (lower id -> higher ids), which is all that is kept of them;
+//      degrees from the run lengths (lower ends) and one atomic per unique edge (higher end);
+//   2. rank by (degree, id) as in the one-pass build;
+//   3. orientation: each canonical edge adds 1 to the out-degree of its lower-ranked end; the
+//      oriented lists are filled through per-row cursors and then sorted row by row;
+//   4. reverse lists in compact form: per kept in-edge (u -> v), u and the position of v in
+//      N+(u) (16 bits; the tail start and length follow from out_off[u] and out_off[u + 1]),
+//      placed through per-vertex cursors.  6 bytes per in-edge instead of 16;
+//   5. statistics and the schedule as in the one-pass build.
+// Peak memory at scale 30 is about 215 GB for the graph plus one phase's temporaries.
+
+namespace {
+
+constexpr int kHistBits = 12;
+constexpr int kEdgeTile = 4096;  // edges per block in the passes over a CSR's entries
+
+// Histogram of the pairs' lower ends by their top kHistBits bits, counted in LDS; blocks stride
+// over the chunk so that each flushes its counts once.
+__global__ __launch_bounds__(kB) void k_stream_hist(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                                    size_t cnt, int64_t n, int shift,
+                                                    unsigned long long* __restrict__ hist, int* __restrict__ bad) {
+    __shared__ unsigned int h[1 << kHistBits];
+    for (int i = threadIdx.x; i < (1 << kHistBits); i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    bool out = false;
+    GRID_STRIDE(i, cnt) {
+        const int32_t a = src[i], b = dst[i];
+        if (a < 0 || a >= n || b < 0 || b >= n) {
+            out = true;
+        } else if (a != b) {
+            atomicAdd(&h[(uint32_t)(a < b ? a : b) >> shift], 1u);
+        }
+    }
+    if (out) *bad = 1;
+    __syncthreads();
+    for (int i = threadIdx.x; i < (1 << kHistBits); i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+// Canonical keys ((lower - lo0) << bits | higher) of the pairs whose lower end lies in
+// [lo0, lo1), appended behind a counter: a block takes kScanTile pairs at a time (element
+// i * 256 + t is thread t's i-th), ranks its keys by ballots and one scan over the (round, wave)
+// counts, and reserves their places with one atomic per tile.  At most `cap` keys are written;
+// the counter still counts every one.  A pair with an end outside [0, n) (a source that changed
+// since the histogram pass) is not taken and raises *bad.
+__global__ __launch_bounds__(kScanThreads) void k_stream_keys(const int32_t* __restrict__ src,
+                                                              const int32_t* __restrict__ dst, size_t cnt, int64_t n,
+                                                              int bits, int64_t lo0, int64_t lo1,
+                                                              uint64_t* __restrict__ keys,
+                                                              unsigned long long* __restrict__ count,
+                                                              unsigned long long cap, int* __restrict__ bad) {
+    constexpr int NW = kScanThreads / kWave;
+    static_assert(kScanItems * NW == kWave, "one lane per (round, wave) count");
+    __shared__ uint32_t base[kScanItems][NW];
+    __shared__ unsigned long long s_base;
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const unsigned long long lt = lanemask_lt();
+    for (size_t tile = (size_t)blockIdx.x * kScanTile; tile < cnt; tile += (size_t)gridDim.x * kScanTile) {
+        uint64_t key[kScanItems];
+        unsigned long long bal[kScanItems];
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const size_t e = tile + (size_t)i * kScanThreads + threadIdx.x;
+            bool take = false;
+            key[i] = 0;
+            if (e < cnt) {
+                const int32_t a = src[e], b = dst[e];
+                const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                if (lo < 0 || hi >= n) *bad = 1;
+                take = a != b && lo >= lo0 && lo < lo1 && hi < n;
+                key[i] = ((uint64_t)(lo - lo0) << bits) | (uint64_t)hi;
+            }
+            bal[i] = __builtin_amdgcn_ballot_w64(take);
+            if (lane == 0) base[i][w] = (uint32_t)__popcll(bal[i]);
+        }
+        __syncthreads();
+        if (w == 0) {
+            const uint32_t c = base[lane / NW][lane % NW];
+            const uint32_t incl = wave_inclusive_scan(c);
+            base[lane / NW][lane % NW] = incl - c;
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+            if (lane == 0) s_base = total ? atomicAdd(count, (unsigned long long)total) : 0ull;
+        }
+        __syncthreads();
+        const unsigned long long b0 = s_base;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if ((bal[i] >> lane) & 1ull) {
+                const unsigned long long p = b0 + base[i][w] + (unsigned long long)__popcll(bal[i] & lt);
+                if (p < cap) keys[p] = key[i];
+            }
+        }
+        __syncthreads();  // base and s_base are rewritten by the next tile
+    }
+}
+
+__global__ void k_hi_degree(const uint32_t* __restrict__ hi, size_t cnt, int32_t* __restrict__ deg) {
+    GRID_STRIDE(i, cnt) atomicAdd(&deg[hi[i]], 1);
+}
+
+__global__ void k_add_i32(int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n) {
+    GRID_STRIDE(i, n) a[i] += b[i];
+}
+
+// The row r of a CSR entry e: the last r in [lo, hi] with off[r] <= e.
+template <typename OffT>
+__device__ __forceinline__ int64_t row_of(const OffT* __restrict__ off, int64_t lo, int64_t hi, size_t e) {
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo + 1) >> 1);
+        if ((size_t)off[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Rows spanned by the entries [e0, e1) of a block (found once per block), so that each entry's
+// row is a short search in cached offsets.
+template <typename OffT>
+__device__ __forceinline__ void block_rows(const OffT* __restrict__ off, int64_t n, size_t e0, size_t e1,
+                                           int64_t* r0, int64_t* r1) {
+    __shared__ int64_t s_r[2];
+    if (threadIdx.x == 0) {
+        s_r[0] = row_of(off, 0, n - 1, e0);
+        s_r[1] = row_of(off, s_r[0], n - 1, e1 - 1);
+    }
+    __syncthreads();
+    *r0 = s_r[0];
+    *r1 = s_r[1];
+    __syncthreads();
+}
+
+// Pass 3a: for each canonical edge (x < y) of the upper lists, +1 to the out-degree of the end
+// of lower rank.
+__global__ __launch_bounds__(256) void k_orient_count(const int64_t* __restrict__ uoff, const int32_t* __restrict__ uadj,
+                                                      int64_t n, size_t m, const int32_t* __restrict__ rank,
+                                                      int32_t* __restrict__ dplus) {
+    for (size_t e0 = (size_t)blockIdx.x * kEdgeTile; e0 < m; e0 += (size_t)gridDim.x * kEdgeTile) {
+        const size_t e1 = e0 + kEdgeTile < m ? e0 + kEdgeTile : m;
+        int64_t r0, r1;
+        block_rows(uoff, n, e0, e1, &r0, &r1);
+        for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const int64_t x = row_of(uoff, r0, r1, e);
+            const int32_t rx = rank[x], ry = rank[uadj[e]];
+            atomicAdd(&dplus[rx < ry ? rx : ry], 1);
+        }
+    }
+}
+
+// Pass 3b: each canonical edge written into its lower-ranked end's oriented list, at the next
+// free place of that row (per-row cursors); the rows are sorted afterwards.
+__global__ __launch_bounds__(256) void k_orient_fill(const int64_t* __restrict__ uoff, const int32_t* __restrict__ uadj,
+                                                     int64_t n, size_t m, const int32_t* __restrict__ rank,
+                                                     const int64_t* __restrict__ out_off, int32_t* __restrict__ cursor,
+                                                     int32_t* __restrict__ adj) {
+    for (size_t e0 = (size_t)blockIdx.x * kEdgeTile; e0 < m; e0 += (size_t)gridDim.x * kEdgeTile) {
+        const size_t e1 = e0 + kEdgeTile < m ? e0 + kEdgeTile : m;
+        int64_t r0, r1;
+        block_rows(uoff, n, e0, e1, &r0, &r1);
+        for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const int64_t x = row_of(uoff, r0, r1, e);
+            const int32_t rx = rank[x], ry = rank[uadj[e]];
+            const int32_t lo = rx < ry ? rx : ry, hi = rx < ry ? ry : rx;
+            const int32_t slot = atomicAdd(&cursor[lo], 1);
+            adj[out_off[lo] + slot] = hi;
+        }
+    }
+}
+
+// Rows of up to 64 int32 entries sorted in registers, G lanes per row (as sort_rows_by_group).
+template <int G>
+__device__ __forceinline__ void sort_rows32_by_group(int32_t* __restrict__ adj, uint64_t todo, int64_t beg, int32_t d) {
+    constexpr int R = kWave / G;
+    const int lane = lane_id(), grp = lane / G, e = lane % G;
+    while (todo) {
+        int js[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            js[q] = todo ? (int)__builtin_ctzll(todo) : -1;
+            todo &= todo - 1;
+        }
+        int jg = js[0];
+#pragma unroll
+        for (int q = 1; q < R; ++q) jg = grp == q ? js[q] : jg;
+        const int jl = jg >= 0 ? jg : 0;
+        const int64_t s = shfl_off(beg, jl);
+        const int32_t dj = __shfl(d, jl, kWave);
+        const bool valid = jg >= 0 && e < dj;
+        uint32_t x = valid ? (uint32_t)adj[s + e] : 0xffffffffu;
+        x = group_bitonic_sort<G>(x);
+        if (valid) adj[s + e] = (int32_t)x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sort_rows32_short(int32_t* __restrict__ adj, const int64_t* __restrict__ off,
+                                                           int64_t n) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r0 = wave * kWave; r0 < n; r0 += nwaves * kWave) {
+        const int64_t r = r0 + lane;
+        int64_t beg = 0;
+        int32_t d = 0;
+        if (r < n) {
+            beg = off[r];
+            d = (int32_t)(off[r + 1] - beg);
+        }
+        sort_rows32_by_group<16>(adj, __builtin_amdgcn_ballot_w64(d > 1 && d <= 16), beg, d);
+        sort_rows32_by_group<32>(adj, __builtin_amdgcn_ballot_w64(d > 16 && d <= 32), beg, d);
+        sort_rows32_by_group<64>(adj, __builtin_amdgcn_ballot_w64(d > 32 && d <= kWave), beg, d);
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void sort_long_row32(int32_t* __restrict__ adj, int64_t s, int32_t d) {
+    const int lane = lane_id();
+    uint32_t v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * kWave + lane;
+        v[e] = i < d ? (uint32_t)adj[s + i] : 0xffffffffu;
+    }
+    reg_bitonic<E>(v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = e * kWave + lane;
+        if (i < d) adj[s + i] = (int32_t)v[e];
+    }
+}
+
+// Listed rows of 65 .. 4096 entries: one wave per row, in registers.
+__global__ __launch_bounds__(256) void k_sort_rows32_long(int32_t* __restrict__ adj, const int64_t* __restrict__ off,
+                                                          const int32_t* __restrict__ rows, int64_t count) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t it = wave; it < count; it += nwaves) {
+        const int32_t r = rows[it];
+        const int64_t s = off[r];
+        const int32_t d = (int32_t)(off[r + 1] - s);
+        if (d <= kWave || d > kRowSortMax) continue;
+        if (d <= 128) sort_long_row32<2>(adj, s, d);
+        else if (d <= 256) sort_long_row32<4>(adj, s, d);
+        else if (d <= 512) sort_long_row32<8>(adj, s, d);
+        else if (d <= 1024) sort_long_row32<16>(adj, s, d);
+        else if (d <= 2048) sort_long_row32<32>(adj, s, d);
+        else sort_long_row32<64>(adj, s, d);
+    }
+}
+
+// Rows longer than the register sort: their entries as (row list index << 32 | value) keys,
+// sorted together, and written back.
+__global__ void k_long_gather(int32_t* __restrict__ adj, const int64_t* __restrict__ off,
+                              const int32_t* __restrict__ rows, const int64_t* __restrict__ kpos, int64_t count,
+                              uint64_t* __restrict__ keys, bool back) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t it = wave; it < count; it += nwaves) {
+        const int32_t r = rows[it];
+        const int64_t s = off[r], d = off[r + 1] - s, k0 = kpos[it];
+        for (int64_t i = lane_id(); i < d; i += kWave) {
+            if (!back) keys[k0 + i] = ((uint64_t)it << 32) | (uint32_t)adj[s + i];
+            else adj[s + i] = (int32_t)(uint32_t)keys[k0 + i];
+        }
+    }
+}
+
+__global__ void k_row_len64(const int32_t* __restrict__ rows, int64_t count, const int32_t* __restrict__ dplus,
+                            int64_t* __restrict__ len) {
+    GRID_STRIDE(i, count) len[i] = dplus[rows[i]];
+}
+
+// Pass 4a: per oriented edge e = (u -> v) at position p of N+(u): an in-edge of v is kept if its
+// tail (the entries of N+(u) after v) and N+(v) are nonempty; counts per v, probes of v, and a
+// flag if a position does not fit 16 bits.
+__global__ __launch_bounds__(256) void k_in_count_compact(const int64_t* __restrict__ out_off,
+                                                          const int32_t* __restrict__ adj, int64_t n, size_t m,
+                                                          const int32_t* __restrict__ dplus, int32_t* __restrict__ din,
+                                                          unsigned long long* __restrict__ work, int* __restrict__ wide) {
+    for (size_t e0 = (size_t)blockIdx.x * kEdgeTile; e0 < m; e0 += (size_t)gridDim.x * kEdgeTile) {
+        const size_t e1 = e0 + kEdgeTile < m ? e0 + kEdgeTile : m;
+        int64_t r0, r1;
+        block_rows(out_off, n, e0, e1, &r0, &r1);
+        for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const int64_t u = row_of(out_off, r0, r1, e);
+            const int64_t pos = (int64_t)e - out_off[u];
+            const int64_t tail = (int64_t)dplus[u] - pos - 1;
+            const int32_t v = adj[e];
+            if (tail > 0 && dplus[v] > 0) {
+                if (pos > 0xffff) *wide = 1;
+                atomicAdd(&din[v], 1);
+                atomicAdd(&work[v], (unsigned long long)tail);
+            }
+        }
+    }
+}
+
+// Pass 4b: the kept in-edges placed through per-vertex cursors: u and the position of v in N+(u).
+__global__ __launch_bounds__(256) void k_in_fill_compact(const int64_t* __restrict__ out_off,
+                                                         const int32_t* __restrict__ adj, int64_t n, size_t m,
+                                                         const int32_t* __restrict__ dplus,
+                                                         const int64_t* __restrict__ in_off, int32_t* __restrict__ cursor,
+                                                         int32_t* __restrict__ in_u, uint16_t* __restrict__ in_pos) {
+    for (size_t e0 = (size_t)blockIdx.x * kEdgeTile; e0 < m; e0 += (size_t)gridDim.x * kEdgeTile) {
+        const size_t e1 = e0 + kEdgeTile < m ? e0 + kEdgeTile : m;
+        int64_t r0, r1;
+        block_rows(out_off, n, e0, e1, &r0, &r1);
+        for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            const int64_t u = row_of(out_off, r0, r1, e);
+            const int64_t pos = (int64_t)e - out_off[u];
+            const int64_t tail = (int64_t)dplus[u] - pos - 1;
+            const int32_t v = adj[e];
+            if (tail > 0 && dplus[v] > 0) {
+                const int64_t k = in_off[v] + atomicAdd(&cursor[v], 1);
+                in_u[k] = (int32_t)u;
+                in_pos[k] = (uint16_t)pos;
+            }
+        }
+    }
+}
+
+unsigned edge_grid(size_t m) {
+    const size_t b = (m + kEdgeTile - 1) / kEdgeTile;
+    return (unsigned)std::max<size_t>(1, std::min<size_t>(b, 65536));
+}
+
+}  // namespace
+
+tc_lcc_status build_streamed(tc_lcc_ctx ctx, int64_t n, uint64_t m_in, const StreamSource& source,
+                             uint64_t chunk, uint64_t part_cap, const tc_lcc_tuning& tn, hipStream_t st,
+                             tc_lcc_graph g) {
+    GraphDev& d = g->d;
+    Pool* pool = ctx->pool.get();
+    Temps tmp{pool, {}};
+    // give a temporary back before the build ends (the stream is idle when this is called)
+    auto drop = [&](void* p) {
+        for (auto it = tmp.held.begin(); it != tmp.held.end(); ++it)
+            if (*it == p) {
+                pool->release(p);
+                tmp.held.erase(it);
+                return;
+            }
+    };
+    const int bits = std::max(1, ceil_log2((uint64_t)n));
+    const size_t N = (size_t)n;
+    d.n = n;
+    d.bits = bits;
+    d.off_bytes = 8;
+    d.compact = true;
+    chunk = std::max<uint64_t>(1, std::min<uint64_t>(chunk, std::max<uint64_t>(m_in, 1)));
+    part_cap = std::max<uint64_t>(part_cap ? part_cap : m_in, 1);
+
+    int32_t *cs, *cd;
+    TCL_TRY(tmp.get(chunk, &cs));
+    TCL_TRY(tmp.get(chunk, &cd));
+    int* bad;  // [0] id outside [0, n), [1] sort gave up, [2] a row position beyond 16 bits
+    TCL_TRY(tmp.get(16, &bad));
+    TCL_HIP(fill<int>(bad, 16, 0, st));
+    unsigned int* sort_err = (unsigned int*)(bad + 1);
+    auto each_chunk = [&](auto&& fn) -> tc_lcc_status {
+        for (uint64_t first = 0; first < m_in; first += chunk) {
+            const uint64_t cnt = std::min<uint64_t>(chunk, m_in - first);
+            const tc_lcc_status s = source(first, cnt, cs, cd, st);
+            if (s != TC_LCC_OK) return s;
+            fn(cnt);
+            TCL_HIP(hipGetLastError());
+        }
+        return TC_LCC_OK;
+    };
+
+    mark(d, 0, st);
+    // 0. histogram of the lower ends -> partitions of at most part_cap pairs
+    const int shift = std::max(0, bits - kHistBits);
+    unsigned long long* hist;
+    TCL_TRY(tmp.get(1 << kHistBits, &hist));
+    TCL_HIP(fill<unsigned long long>(hist, 1 << kHistBits, 0ull, st));
+    TCL_TRY(each_chunk([&](uint64_t cnt) {
+        k_stream_hist<<<grid_for(cnt, kB, 512), kB, 0, st>>>(cs, cd, cnt, n, shift, hist, bad);
+    }));
+    std::vector<unsigned long long> hh(1 << kHistBits);
+    int hbad = 0;
+    TCL_HIP(hipMemcpyAsync(hh.data(), hist, hh.size() * 8, hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipStreamSynchronize(st));
+    if (hbad) {
+        set_error("tc_lcc_build_streamed: an endpoint lies outside [0, %lld)", (long long)n);
+        return TC_LCC_INVALID_ARGUMENT;
+    }
+    // partitions: consecutive bins while they hold at most part_cap pairs together (a single
+    // bin above part_cap is a partition of its own)
+    std::vector<int64_t> bounds{0};
+    unsigned long long kmax = 0;
+    int64_t span_max = 1;
+    {
+        unsigned long long acc = 0;
+        for (size_t b = 0; b < hh.size(); ++b) {
+            if (acc > 0 && acc + hh[b] > part_cap) {
+                bounds.push_back(std::min<int64_t>((int64_t)b << shift, n));
+                kmax = std::max(kmax, acc);
+                acc = 0;
+            }
+            acc += hh[b];
+        }
+        bounds.push_back(n);
+        kmax = std::max(kmax, acc);
+        for (size_t p = 0; p + 1 < bounds.size(); ++p) span_max = std::max(span_max, bounds[p + 1] - bounds[p]);
+    }
+    if (kmax >= (1ull << 32)) {
+        set_error("tc_lcc_build_streamed: %llu pairs fall into one partition (at most 2^32 - 1)", kmax);
+        return TC_LCC_UNSUPPORTED;
+    }
+    drop(hist);
+
+    // 1. per partition: keys, sort, unique, upper lists, degrees
+    const size_t K = std::max<size_t>((size_t)kmax, 1);
+    int32_t* uadj;
+    TCL_TRY(tmp.get(std::max<uint64_t>(m_in, 1), &uadj));
+    int32_t *ucnt, *deg;
+    TCL_TRY(tmp.get(N, &ucnt));
+    TCL_TRY(tmp.get(N, &deg));
+    TCL_HIP(fill<int32_t>(ucnt, N, 0, st));
+    TCL_HIP(fill<int32_t>(deg, N, 0, st));
+    uint64_t *ka, *kb, *kc;
+    uint32_t *hi_ends, *toff, *f1, *l1;
+    TCL_TRY(tmp.get(K + 1, &ka));
+    TCL_TRY(tmp.get(K + 1, &kb));
+    TCL_TRY(tmp.get(K + 1, &kc));
+    TCL_TRY(tmp.get(K + 1, &hi_ends));
+    const size_t tiles_max = (K + kScanTile - 1) / kScanTile;
+    TCL_TRY(tmp.get(tiles_max + 2, &toff));
+    TCL_TRY(tmp.get((size_t)span_max + 1, &f1));
+    TCL_TRY(tmp.get((size_t)span_max + 1, &l1));
+    void* sort_scratch;
+    const size_t rs_bytes = radix_sort_scratch_bytes(std::max(K, N));
+    const size_t scan_elems = scan_scratch_elems(std::max(K, N) + 1);
+    TCL_TRY(tmp.get(rs_bytes + sizeof(uint64_t) * scan_elems + 1024, (uint8_t**)&sort_scratch));
+    uint32_t* scan32 = (uint32_t*)((uint8_t*)sort_scratch + rs_bytes);
+    int64_t* scan64 = (int64_t*)scan32;
+    unsigned long long* kcount;
+    TCL_TRY(tmp.get(2, &kcount));
+    size_t mtot = 0;
+    for (size_t p = 0; p + 1 < bounds.size(); ++p) {
+        const int64_t lo0 = bounds[p], lo1 = bounds[p + 1];
+        if (lo1 <= lo0) continue;
+        TCL_HIP(fill<unsigned long long>(kcount, 2, 0ull, st));
+        TCL_TRY(each_chunk([&](uint64_t cnt) {
+            const size_t ktiles = (cnt + kScanTile - 1) / kScanTile;
+            k_stream_keys<<<(unsigned)std::min<size_t>(ktiles, 8192), kScanThreads, 0, st>>>(
+                cs, cd, cnt, n, bits, lo0, lo1, ka, kcount, K, bad);
+        }));
+        unsigned long long kp = 0;
+        int pbad = 0;
+        TCL_HIP(hipMemcpyAsync(&kp, kcount, 8, hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipMemcpyAsync(&pbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipStreamSynchronize(st));
+        if (kp > K || pbad) {
+            set_error("tc_lcc_build_streamed: the pair source gave different pairs on two passes");
+            return TC_LCC_INVALID_ARGUMENT;
+        }
+        if (kp == 0) continue;
+        const int lbits = std::max(1, ceil_log2((uint64_t)(lo1 - lo0)));
+        uint64_t* sorted = ka;
+        TCL_HIP(radix_sort_u64(ka, kb, kp, 0, bits + lbits, sort_scratch, sort_err, st, &sorted));
+        const size_t tiles = (kp + kScanTile - 1) / kScanTile;
+        k_reduce_tiles<uint32_t, UniqueFlag><<<(unsigned)tiles, kScanThreads, 0, st>>>(
+            UniqueFlag{sorted, (size_t)kp, (1ull << (2 * bits)) - 1}, kp, toff);
+        TCL_HIP(hipGetLastError());
+        TCL_HIP(exclusive_scan<uint32_t>(ArrayIn<uint32_t>{toff, tiles}, tiles + 1, toff, scan32, st));
+        k_unique_tiles<<<(unsigned)tiles, kScanThreads, 0, st>>>(sorted, kp, bits, toff, kc, hi_ends);
+        TCL_HIP(hipGetLastError());
+        uint32_t up = 0;
+        TCL_HIP(hipMemcpyAsync(&up, toff + tiles, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipStreamSynchronize(st));
+        if (mtot + up > m_in) {
+            set_error("tc_lcc_build_streamed: the pair source gave different pairs on two passes");
+            return TC_LCC_INVALID_ARGUMENT;
+        }
+        TCL_HIP(hipMemcpyAsync(uadj + mtot, hi_ends, (size_t)up * 4, hipMemcpyDeviceToDevice, st));
+        // run lengths per lower end: the upper-list lengths of the partition's ids
+        TCL_HIP(run_bounds(GroupShift{kc, bits}, up, f1, l1, lo1 - lo0, st));
+        k_run_counts<<<grid_for((size_t)(lo1 - lo0), kB, 8192), kB, 0, st>>>(f1, l1, lo1 - lo0, ucnt + lo0);
+        k_hi_degree<<<grid_for(up, kB, 8192), kB, 0, st>>>(hi_ends, up, deg);
+        TCL_HIP(hipGetLastError());
+        mtot += up;
+    }
+    TCL_HIP(hipStreamSynchronize(st));
+    for (void* p : {(void*)ka, (void*)kb, (void*)kc, (void*)hi_ends, (void*)cs, (void*)cd, (void*)f1, (void*)l1}) drop(p);
+    const size_t m = mtot;
+    d.m = (int64_t)m;
+    int64_t* uoff;
+    TCL_TRY(tmp.get(N + 1, &uoff));
+    TCL_HIP(exclusive_scan<int64_t>(I32In<int64_t>{ucnt, n}, N + 1, uoff, scan64, st));
+    k_add_i32<<<grid_for(N, kB, 8192), kB, 0, st>>>(deg, ucnt, n);
+    TCL_HIP(hipGetLastError());
+    TCL_HIP(hipStreamSynchronize(st));
+    drop(ucnt);
+
+    mark(d, 1, st);
+    // 2. rank by (degree, id)
+    int32_t* rank;
+    TCL_TRY(tmp.get(N, &rank));
+    TCL_TRY(keep(g, N, &d.order));
+    TCL_TRY(keep(g, N, &d.deg_r));
+    {
+        uint64_t *ra, *rb2;
+        TCL_TRY(tmp.get(N + 1, &ra));
+        TCL_TRY(tmp.get(N + 1, &rb2));
+        uint64_t* rs = ra;
+        k_rank_keys<<<grid_for(N, kB, 8192), kB, 0, st>>>(deg, n, bits, ra);
+        TCL_HIP(hipGetLastError());
+        TCL_HIP(radix_sort_u64(ra, rb2, N, bits, bits, sort_scratch, sort_err, st, &rs));
+        k_rank_scatter<<<grid_for(N, kB, 8192), kB, 0, st>>>(rs, n, bits, d.order, rank, d.deg_r);
+        TCL_HIP(hipGetLastError());
+        TCL_HIP(hipStreamSynchronize(st));
+        drop(ra);
+        drop(rb2);
+    }
+    drop(deg);
+
+    mark(d, 2, st);
+    // 3. orientation: out-degrees, offsets, fill through cursors, sort the rows
+    TCL_TRY(keep(g, N, &d.dplus));
+    int64_t* out_off;
+    TCL_TRY(keep(g, N + 1, &out_off));
+    d.out_off = out_off;
+    TCL_TRY(keep(g, std::max<size_t>(m, 1), &d.adj));
+    int32_t* cursor;
+    TCL_TRY(tmp.get(N, &cursor));
+    TCL_HIP(fill<int32_t>(d.dplus, N, 0, st));
+    TCL_HIP(fill<int32_t>(cursor, N, 0, st));
+    if (m > 0) {
+        k_orient_count<<<edge_grid(m), 256, 0, st>>>(uoff, uadj, n, m, rank, d.dplus);
+        TCL_HIP(hipGetLastError());
+    }
+    TCL_HIP(exclusive_scan<int64_t>(I32In<int64_t>{d.dplus, n}, N + 1, out_off, scan64, st));
+    if (m > 0) {
+        k_orient_fill<<<edge_grid(m), 256, 0, st>>>(uoff, uadj, n, m, rank, out_off, cursor, d.adj);
+        TCL_HIP(hipGetLastError());
+    }
+    TCL_HIP(hipStreamSynchronize(st));
+    drop(uadj);
+    drop(uoff);
+    drop(rank);
+    int dmax = 0;
+    if (m > 0) {
+        int* mx = bad + 4;
+        k_max_i32<<<grid_for(N, kB, 1024), kB, 0, st>>>(d.dplus, n, mx);
+        TCL_HIP(hipGetLastError());
+        TCL_HIP(hipMemcpyAsync(&dmax, mx, sizeof(int), hipMemcpyDeviceToHost, st));
+        const size_t groups = (N + kWave - 1) / kWave;
+        k_sort_rows32_short<<<grid_for(groups * kWave, kB, 8192), kB, 0, st>>>(d.adj, out_off, n);
+        TCL_HIP(hipGetLastError());
+        // the longer rows, listed by a scan of their flags
+        uint32_t* rpos;
+        TCL_TRY(tmp.get(N + 1, &rpos));
+        TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n, kWave}, N + 1, rpos, scan32, st));
+        uint32_t nlong = 0;
+        TCL_HIP(hipMemcpyAsync(&nlong, rpos + N, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        TCL_HIP(hipStreamSynchronize(st));
+        if (nlong > 0) {
+            int32_t* rows;
+            TCL_TRY(tmp.get(nlong, &rows));
+            k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, kWave, rpos, rows);
+            k_sort_rows32_long<<<grid_for((size_t)nlong * kWave, kB, 8192), kB, 0, st>>>(d.adj, out_off, rows,
+                                                                                        (int64_t)nlong);
+            TCL_HIP(hipGetLastError());
+        }
+        if (dmax > kRowSortMax) {
+            // rows beyond the register sort: gathered as (list index << 32 | value), sorted, put back
+            uint32_t* rpos2;
+            TCL_TRY(tmp.get(N + 1, &rpos2));
+            TCL_HIP(exclusive_scan<uint32_t>(LongRow{d.dplus, n, kRowSortMax}, N + 1, rpos2, scan32, st));
+            uint32_t nvery = 0;
+            TCL_HIP(hipMemcpyAsync(&nvery, rpos2 + N, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            TCL_HIP(hipStreamSynchronize(st));
+            int32_t* vrows;
+            int64_t *vlen, *vpos;
+            TCL_TRY(tmp.get(std::max<uint32_t>(nvery, 1), &vrows));
+            TCL_TRY(tmp.get(std::max<uint32_t>(nvery, 1), &vlen));
+            TCL_TRY(tmp.get((size_t)nvery + 1, &vpos));
+            k_list_rows<<<grid_for(N, kB, 8192), kB, 0, st>>>(d.dplus, n, kRowSortMax, rpos2, vrows);
+            k_row_len64<<<grid_for(nvery, kB, 1024), kB, 0, st>>>(vrows, nvery, d.dplus, vlen);
+            TCL_HIP(hipGetLastError());
+            TCL_HIP(exclusive_scan<int64_t>(ArrayIn<int64_t>{vlen, nvery}, (size_t)nvery + 1, vpos, scan64, st));
+            int64_t tot = 0;
+            TCL_HIP(hipMemcpyAsync(&tot, vpos + nvery, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            TCL_HIP(hipStreamSynchronize(st));
+            uint64_t *va, *vb;
+            TCL_TRY(tmp.get((size_t)tot + 1, &va));
+            TCL_TRY(tmp.get((size_t)tot + 1, &vb));
+            void* vscr;
+            TCL_TRY(tmp.get(radix_sort_scratch_bytes((size_t)tot), (uint8_t**)&vscr));
+            k_long_gather<<<grid_for((size_t)nvery * kWave, kB, 4096), kB, 0, st>>>(d.adj, out_off, vrows, vpos,
+                                                                                    nvery, va, false);
+            uint64_t* vs = va;
+            TCL_HIP(radix_sort_u64(va, vb, (size_t)tot, 0, 32 + std::max(1, ceil_log2(nvery)), vscr, sort_err, st,
+                                   &vs));
+            k_long_gather<<<grid_for((size_t)nvery * kWave, kB, 4096), kB, 0, st>>>(d.adj, out_off, vrows, vpos,
+                                                                                    nvery, vs, true);
+            TCL_HIP(hipGetLastError());
+        }
+    }
+    TCL_HIP(hipStreamSynchronize(st));
+    drop(cursor);
+
+    mark(d, 3, st);
+    // 4. reverse lists in compact form
+    int32_t* din;
+    TCL_TRY(tmp.get(N, &din));
+    TCL_HIP(fill<int32_t>(din, N, 0, st));
+    TCL_TRY(keep(g, N, &d.work));
+    TCL_HIP(fill<uint64_t>(d.work, N, 0ull, st));
+    if (m > 0) {
+        k_in_count_compact<<<edge_grid(m), 256, 0, st>>>(out_off, d.adj, n, m, d.dplus, din,
+                                                         (unsigned long long*)d.work, bad + 2);
+        TCL_HIP(hipGetLastError());
+    }
+    int64_t* in_off;
+    TCL_TRY(keep(g, N + 1, &in_off));
+    d.in_off = in_off;
+    TCL_HIP(exclusive_scan<int64_t>(I32In<int64_t>{din, n}, N + 1, in_off, scan64, st));
+    int64_t kept = 0;
+    int wide = 0;
+    TCL_HIP(hipMemcpyAsync(&kept, in_off + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipMemcpyAsync(&wide, bad + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipStreamSynchronize(st));
+    if (wide) {
+        set_error("tc_lcc_build_streamed: an oriented list longer than 65536 entries (compact in-edges hold "
+                  "16-bit positions)");
+        return TC_LCC_UNSUPPORTED;
+    }
+    d.m_in_kept = kept;
+    const size_t KE = std::max<size_t>((size_t)kept, 1);
+    TCL_TRY(keep(g, KE, &d.in_u));
+    TCL_TRY(keep(g, KE, &d.in_pos));
+    TCL_HIP(fill<int32_t>(din, N, 0, st));  // the cursors
+    if (m > 0) {
+        k_in_fill_compact<<<edge_grid(m), 256, 0, st>>>(out_off, d.adj, n, m, d.dplus, in_off, din, d.in_u, d.in_pos);
+        TCL_HIP(hipGetLastError());
+    }
+    TCL_HIP(hipStreamSynchronize(st));
+    drop(din);
+
+    mark(d, 4, st);
+    // 5. run scratch and statistics
+    TCL_TRY(keep(g, N, &d.t_rank));
+    TCL_TRY(keep(g, 64, &d.counters));
+    TCL_TRY(keep(g, N, &d.vlist));
+    unsigned long long* stats;
+    TCL_TRY(tmp.get(8, &stats));
+    TCL_HIP(fill<unsigned long long>(stats, 8, 0ull, st));
+    k_stats<<<grid_for(N, kB, 2048), kB, 0, st>>>(d.dplus, d.deg_r, (const unsigned long long*)d.work, n, stats);
+    TCL_HIP(hipGetLastError());
+    unsigned long long hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int serr = 0;
+    TCL_HIP(hipMemcpyAsync(hs, stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipMemcpyAsync(&serr, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    TCL_HIP(hipStreamSynchronize(st));
+    if (serr) {
+        set_error("tc_lcc_build_streamed: a radix sort pass gave up waiting for an earlier tile");
+        return TC_LCC_DEVICE_ERROR;
+    }
+    d.max_dplus = (int32_t)hs[0];
+    d.max_deg = (int64_t)hs[1];
+    d.wedges = hs[2];
+    d.staged = hs[3];
+    d.push_words = hs[4];
+    tc_lcc_status s = build_schedule(g, tn, st);
+    mark(d, 5, st);
+    return s;
+}
+
 }  // namespace tcl

@@ -144,6 +144,7 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, int merge_x100, int spare_per_
     a.in_u = d.in_u;
     a.in_start = (const OffT*)d.in_start;
     a.in_len = d.in_len;
+    a.in_pos = d.in_pos;
     a.vlist = d.vlist;
     a.n_block = d.n_block;
     a.n_wave = d.n_wave;
@@ -202,6 +203,7 @@ static tc_lcc_status launch_typed(tc_lcc_graph g, int merge_x100, int spare_per_
 }
 
 tc_lcc_status launch_count(tc_lcc_graph g, const tc_lcc_tuning& tn, int spare_per_cu, hipStream_t st) {
+    if (g->d.compact) return launch_typed<OffCompact>(g, tn.merge_ratio_x100, spare_per_cu, st);
     return g->d.off_bytes == 4 ? launch_typed<int32_t>(g, tn.merge_ratio_x100, spare_per_cu, st)
                                : launch_typed<int64_t>(g, tn.merge_ratio_x100, spare_per_cu, st);
 }

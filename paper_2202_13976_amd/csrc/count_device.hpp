@@ -17,6 +17,7 @@ struct CountArgs {
     const int32_t* in_u;
     const OffT* in_start;
     const int32_t* in_len;
+    const uint16_t* in_pos;  // compact reverse lists (OffT = OffCompact): position of v in N+(u)
     const int32_t* vlist;
     int64_t n_block, n_wave, n_global;
     unsigned long long* t;
@@ -173,6 +174,21 @@ struct InEdges {
     int32_t len;
 };
 
+// In-edge k: u, the start of its tail in adj and the tail's length.  Compact reverse lists
+// hold u and the position p of v in N+(u); the tail is N+(u) after p.
+template <typename OffT>
+__device__ __forceinline__ void load_in_edge(const CountArgs<OffT>& a, OffT k, int32_t& u, OffT& st, int32_t& len) {
+    u = a.in_u[k];
+    if constexpr (kCompactOff<OffT>) {
+        const OffT o0 = a.out_off[u], o1 = a.out_off[u + 1];
+        st = o0 + (OffT)a.in_pos[k] + 1;
+        len = (int32_t)(o1 - st);
+    } else {
+        st = a.in_start[k];
+        len = a.in_len[k];
+    }
+}
+
 template <int NWAVES, typename OffT>
 __device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a, OffT i0, OffT i1, int wig) {
     InEdges<OffT> e;
@@ -182,11 +198,7 @@ __device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a
     e.st = 0;
     e.len = 0;
     const OffT k = e.i0 + (OffT)lane_id() * NWAVES + wig;
-    if (k < e.i1) {
-        e.u = a.in_u[k];
-        e.st = a.in_start[k];
-        e.len = a.in_len[k];
-    }
+    if (k < e.i1) load_in_edge(a, k, e.u, e.st, e.len);
     return e;
 }
 
@@ -227,11 +239,7 @@ __device__ void walk_tails(const CountArgs<OffT>& a, const InEdges<OffT>& ie, co
         const int32_t u = nu;
         const OffT st = nst;
         const int32_t len = nlen;
-        if (k + kSpan < i1) {
-            nu = a.in_u[k + kSpan];
-            nst = a.in_start[k + kSpan];
-            nlen = a.in_len[k + kSpan];
-        }
+        if (k + kSpan < i1) load_in_edge(a, k + kSpan, nu, nst, nlen);
         // lanes of this wave holding an in-edge of the chunk
         const OffT rest = i1 - cb - wig;
         const int nk = (int)__builtin_amdgcn_readfirstlane(
@@ -385,11 +393,7 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
         int32_t u = 0;
         OffT st = 0;
         int32_t len = 0;
-        if (k < i1) {
-            u = a.in_u[k];
-            st = a.in_start[k];
-            len = a.in_len[k];
-        }
+        if (k < i1) load_in_edge(a, k, u, st, len);
         const int nk = (int)__builtin_amdgcn_readfirstlane((int)min((OffT)kWave, i1 - cb));
         for (int j = wig; j < nk; j += NWAVES) {
             const int32_t tu = lane_value(u, j);
@@ -482,11 +486,7 @@ __device__ void walk_flat(const CountArgs<OffT>& a, const InEdges<OffT>& ie, con
             u = 0;
             st = 0;
             len = 0;
-            if (k < i1) {
-                u = a.in_u[k];
-                st = a.in_start[k];
-                len = a.in_len[k];
-            }
+            if (k < i1) load_in_edge(a, k, u, st, len);
         }
         const int32_t incl = wave_inclusive_scan(len);
         const int32_t excl = incl - len;

@@ -4,10 +4,12 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -15,6 +17,15 @@
 #include "common.hpp"
 
 namespace tcl {
+
+// 64-bit offsets of a graph whose reverse lists are compact (u and a 16-bit row position per
+// in-edge instead of u, tail start and tail length): a type of its own, so that kernels
+// instantiated for it read the compact form (kCompactOff) and those for int64_t do not.
+using OffCompact = long long;
+static_assert(sizeof(OffCompact) == 8, "64-bit offsets");
+static_assert(!std::is_same<OffCompact, int64_t>::value, "OffCompact must differ from int64_t");
+template <typename OffT>
+constexpr bool kCompactOff = std::is_same<OffT, OffCompact>::value;
 
 // count kernel geometry: 256-thread blocks (4 waves); one block per heavy vertex,
 // one wave per light vertex, each with an LDS table of N+(v).
@@ -80,6 +91,10 @@ struct GraphDev {
     int32_t* in_u = nullptr;    // [m_in_kept] u of each in-edge
     void* in_start = nullptr;   // [m_in_kept] position in adj right after v inside N+(u)
     int32_t* in_len = nullptr;  // [m_in_kept] length of that tail of N+(u)
+    // compact reverse lists (streamed build): in_start and in_len are absent; in_pos holds
+    // the position of v in N+(u), so the tail is out_off[u] + in_pos + 1 .. out_off[u + 1]
+    bool compact = false;
+    uint16_t* in_pos = nullptr;  // [m_in_kept]
     int64_t m_in_kept = 0;
     int32_t* order = nullptr;   // [n] original id of rank r
     int32_t* deg_r = nullptr;   // [n] degree of rank r
@@ -159,6 +174,11 @@ tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
                           const int32_t* dst, int inputs_on_device, int offset_bytes,
                           const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g, bool directed = false);
 tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_t st);
+// the streamed, partitioned build (compact reverse lists); source(first, count, src, dst, st)
+// writes pairs [first, first + count) into the device buffers, ordered before later work on st
+using StreamSource = std::function<tc_lcc_status(uint64_t, uint64_t, int32_t*, int32_t*, hipStream_t)>;
+tc_lcc_status build_streamed(tc_lcc_ctx ctx, int64_t n, uint64_t m_in, const StreamSource& source, uint64_t chunk,
+                             uint64_t part_cap, const tc_lcc_tuning& tn, hipStream_t st, tc_lcc_graph g);
 
 // count.hip
 // spare_per_cu: resident blocks per CU left free for other streams' kernels (0 = fill the GPU)
@@ -187,8 +207,8 @@ tc_lcc_status batch_fence_graph(tc_lcc_ctx ctx, tc_lcc_graph g, hipStream_t st);
 // launches ignore theirs); they are zero again once the graph's done flag is up
 tc_lcc_status batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_graph* graphs, uint64_t* const* tri,
                                 double* const* lcc, unsigned long long* const* scratch, tc_lcc_ticket* out);
-// whether a batch runs g through the single-graph launches (directed, or lists longer than a
-// block's hash)
+// whether a batch runs g through the single-graph launches (directed, compact reverse lists, or
+// lists longer than a block's hash)
 bool batch_graph_solo(tc_lcc_graph g);
 // grow every idle slot's descriptors and flags to `graphs` entries now, so that later
 // submissions of up to that many graphs with caller-given counters allocate nothing

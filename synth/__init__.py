@@ -20,18 +20,28 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "synth.c")
 _LIB = os.path.join(_HERE, "libsynth.so")
+_GPU_SRC = os.path.join(_HERE, "synth_gpu.hip")
+_GPU_LIB = os.path.join(_HERE, "libsynth_gpu.so")
 _lib = None
+_gpu_lib = None
 
 RMAT_ABC = (0.57, 0.19, 0.19)
 
 
 def build(force: bool = True) -> str:
-    """Compile the generator library with gcc (OpenMP for the parallel draws)."""
+    """Compile the generator library with gcc (OpenMP for the parallel draws), and its GPU twin
+    for the large-scale recipe with hipcc (gfx950)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_GPU_LIB) or os.path.getmtime(_GPU_LIB) < os.path.getmtime(_GPU_SRC):
+        tmp = _GPU_LIB + ".tmp"
+        subprocess.check_call(["/opt/rocm/bin/hipcc", "-O3", "-fPIC", "-shared", "--offload-arch=gfx950",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               "-o", tmp, _GPU_SRC], stderr=subprocess.DEVNULL)
+        os.replace(tmp, _GPU_LIB)
     return _LIB
 
 
@@ -53,6 +63,14 @@ def _load():
         lib.synth_splitmix64_at.restype = u64
         lib.synth_splitmix64_fill.argtypes = [u64, u64, i64, ctypes.c_void_p]
         lib.synth_splitmix64_fill.restype = None
+        lib.synth_rmat_feistel.argtypes = [ctypes.c_int, f64, f64, f64, u64, u64, i64, p32, p32]
+        lib.synth_rmat_feistel.restype = ctypes.c_int
+        lib.synth_rmat_stream.argtypes = [u64]
+        lib.synth_rmat_stream.restype = u64
+        lib.synth_feistel_keys.argtypes = [u64, ctypes.c_void_p]
+        lib.synth_feistel_keys.restype = None
+        lib.synth_rmat_thresholds.argtypes = [f64, f64, f64, ctypes.c_void_p]
+        lib.synth_rmat_thresholds.restype = None
         _lib = lib
     return _lib
 
@@ -173,6 +191,69 @@ def dense_core(parts: int, size: int, drop: float, periphery_scale: int, seed: i
         parts_s += [ps + nc, (p + nc).astype(np.int32), (p + nc).astype(np.int32)]
         parts_d += [pd + nc, ((7 * p) % nc).astype(np.int32), ((13 * p + 1) % nc).astype(np.int32)]
     return nc + npp, np.concatenate(parts_s).astype(np.int32), np.concatenate(parts_d).astype(np.int32)
+
+
+def rmat_feistel(scale: int, first: int, count: int, seed: int = 1, abc=RMAT_ABC):
+    """Pairs first .. first + count - 1 of the large-scale R-MAT recipe (synth_rmat_feistel):
+    n = 2^scale (scale even), pair e = R-MAT attempt e, ends relabelled by a seeded Feistel
+    bijection.  The workload of scale s and edge factor EF is pairs 0 .. EF * 2^s - 1."""
+    src = np.empty(count, dtype=np.int32)
+    dst = np.empty(count, dtype=np.int32)
+    rc = _load().synth_rmat_feistel(scale, abc[0], abc[1], abc[2], seed, first, count, _p32(src), _p32(dst))
+    if rc != 0:
+        raise ValueError(f"synth_rmat_feistel failed ({rc}) for scale {scale}")
+    return src, dst
+
+
+def _gpu():
+    global _gpu_lib
+    if _gpu_lib is None:
+        if not os.path.exists(_GPU_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_GPU_LIB)
+        vp, u64, i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64
+        lib.synth_gpu_rmat_feistel.argtypes = [ctypes.c_int, u64, vp, vp, u64, i64, vp, vp, vp]
+        lib.synth_gpu_rmat_feistel.restype = ctypes.c_int
+        lib.synth_gpu_copy_i32.argtypes = [vp, vp, i64, vp]
+        lib.synth_gpu_copy_i32.restype = ctypes.c_int
+        _gpu_lib = lib
+    return _gpu_lib
+
+
+class GpuRmatFeistel:
+    """The same recipe written by the GPU into device memory: gen(first, count, src_ptr,
+    dst_ptr, stream_ptr) fills int32 device arrays (plain integer addresses)."""
+
+    def __init__(self, scale: int, seed: int = 1, abc=RMAT_ABC):
+        self.scale = scale
+        self.state = int(_load().synth_rmat_stream(seed))
+        self.thr = np.empty(3, dtype=np.uint64)
+        _load().synth_rmat_thresholds(abc[0], abc[1], abc[2], self.thr.ctypes.data)
+        self.keys = np.empty(4, dtype=np.uint64)
+        _load().synth_feistel_keys(seed, self.keys.ctypes.data)
+
+    def gen(self, first: int, count: int, src_ptr: int, dst_ptr: int, stream_ptr: int = 0):
+        rc = _gpu().synth_gpu_rmat_feistel(self.scale, self.state, self.thr.ctypes.data, self.keys.ctypes.data,
+                                           first, count, src_ptr, dst_ptr, stream_ptr)
+        if rc != 0:
+            raise RuntimeError(f"synth_gpu_rmat_feistel failed ({rc})")
+
+
+class DevicePairs:
+    """Stored pairs in device memory (two int32 torch CUDA tensors) served in chunks:
+    gen(first, count, src_ptr, dst_ptr, stream_ptr) copies pairs [first, first + count)."""
+
+    def __init__(self, src, dst):
+        assert src.dtype == dst.dtype and src.element_size() == 4 and src.numel() == dst.numel()
+        self.src, self.dst = src, dst
+
+    def gen(self, first: int, count: int, src_ptr: int, dst_ptr: int, stream_ptr: int = 0):
+        if first < 0 or first + count > self.src.numel():
+            raise IndexError(f"pairs [{first}, {first + count}) outside [0, {self.src.numel()})")
+        for a, b in ((self.src, src_ptr), (self.dst, dst_ptr)):
+            rc = _gpu().synth_gpu_copy_i32(a.data_ptr() + 4 * first, b, count, stream_ptr)
+            if rc != 0:
+                raise RuntimeError(f"synth_gpu_copy_i32 failed ({rc})")
 
 
 def make(spec):

@@ -33,7 +33,7 @@ static inline uint64_t sm_at(uint64_t s, uint64_t k) { return sm_mix(s + (k + 1)
 /* independent sub-streams of one user seed */
 static inline uint64_t sub_seed(uint64_t seed, uint64_t tag) { return sm_mix(seed ^ (tag * SM_GAMMA)); }
 
-enum { TAG_RMAT = 1, TAG_PERM = 2, TAG_ER = 3 };
+enum { TAG_RMAT = 1, TAG_PERM = 2, TAG_ER = 3, TAG_FEISTEL = 4 };
 
 uint64_t synth_splitmix64_at(uint64_t state, uint64_t k) { return sm_at(state, k); }
 
@@ -149,6 +149,58 @@ int synth_er(int64_t n, int64_t m_gen, uint64_t seed, int32_t* src, int32_t* dst
         uint64_t r = sm_at(s, (uint64_t)e);
         src[e] = (int32_t)(((r >> 32) * (uint64_t)n) >> 32);
         dst[e] = (int32_t)(((r & 0xffffffffULL) * (uint64_t)n) >> 32);
+    }
+    return 0;
+}
+
+/*
+ * The R-MAT workload for very large scales, generated in any range of pair numbers.
+ * Pair e is R-MAT attempt e at `scale` levels (n = 2^scale, no rejection), with both ends
+ * relabelled by a seeded bijection of [0, n) instead of the Fisher-Yates permutation, so that
+ * any range of pairs is produced without a whole-graph pass: a 4-round balanced Feistel
+ * network on the scale/2 high and low bits (scale even), round r's function being
+ * mix(right + key_r) masked to scale/2 bits, key_r = output r of the Feistel stream.
+ * Writes pairs first .. first + count - 1.  Returns 0, or -1 for an odd or out-of-range scale.
+ */
+static inline uint64_t feistel(uint64_t x, int half, const uint64_t* key) {
+    const uint64_t mask = (1ULL << half) - 1;
+    uint64_t l = x >> half, r = x & mask;
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t f = sm_mix(r + key[i]) & mask;
+        const uint64_t nl = r;
+        r = l ^ f;
+        l = nl;
+    }
+    return (l << half) | r;
+}
+
+uint64_t synth_rmat_stream(uint64_t seed) { return sub_seed(seed, TAG_RMAT); }
+
+void synth_feistel_keys(uint64_t seed, uint64_t* key) {
+    const uint64_t s = sub_seed(seed, TAG_FEISTEL);
+    for (int i = 0; i < 4; ++i) key[i] = sm_at(s, (uint64_t)i);
+}
+
+void synth_rmat_thresholds(double a, double b, double c, uint64_t* t) {
+    const quad_t q = make_quad(a, b, c);
+    t[0] = q.t0;
+    t[1] = q.t1;
+    t[2] = q.t2;
+}
+
+int synth_rmat_feistel(int scale, double a, double b, double c, uint64_t seed, uint64_t first, int64_t count,
+                       int32_t* src, int32_t* dst) {
+    if (scale < 2 || scale > 30 || (scale & 1) || count < 0) return -1;
+    const quad_t q = make_quad(a, b, c);
+    const uint64_t s = sub_seed(seed, TAG_RMAT);
+    uint64_t key[4];
+    synth_feistel_keys(seed, key);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; ++i) {
+        int64_t u, v;
+        rmat_pair(s, first + (uint64_t)i, scale, q, &u, &v);
+        src[i] = (int32_t)feistel((uint64_t)u, scale / 2, key);
+        dst[i] = (int32_t)feistel((uint64_t)v, scale / 2, key);
     }
     return 0;
 }

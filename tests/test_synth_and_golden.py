@@ -52,6 +52,43 @@ def test_non_power_of_two_rmat_in_range():
     assert s.min() >= 0 and d.min() >= 0 and s.max() < 1000 and d.max() < 1000
 
 
+def test_rmat_feistel_is_the_rmat_graph_relabelled():
+    """The large-scale recipe draws the same R-MAT attempts as synth.rmat at a power of two and
+    only relabels them, by a bijection: ids map one to one between the two, pair for pair."""
+    scale = 12
+    n, s0, d0 = synth.rmat_scale(scale, 16, seed=5)
+    s1, d1 = synth.rmat_feistel(scale, 0, 16 * n, seed=5)
+    a = np.concatenate([s0, d0]).astype(np.int64)
+    b = np.concatenate([s1, d1]).astype(np.int64)
+    assert b.min() >= 0 and b.max() < n
+    fwd = np.full(n, -1, dtype=np.int64)
+    fwd[a] = b
+    assert np.array_equal(fwd[a], b), "one rmat id maps to two relabelled ids"
+    used = fwd[fwd >= 0]
+    assert len(np.unique(used)) == len(used), "two rmat ids map to one relabelled id"
+    # any range of pairs on its own equals the same slice of the whole sequence
+    s2, d2 = synth.rmat_feistel(scale, 1000, 5003, seed=5)
+    assert np.array_equal(s2, s1[1000:6003]) and np.array_equal(d2, d1[1000:6003])
+    assert not np.array_equal(synth.rmat_feistel(scale, 0, 64, seed=6)[0], s1[:64])
+    with pytest.raises(ValueError):
+        synth.rmat_feistel(13, 0, 10, seed=5)
+
+
+def test_rmat_feistel_triangles_equal_rmat_triangles():
+    """Relabelling changes no triangle count: the per-vertex counts agree through the id map."""
+    scale = 10
+    n, s0, d0 = synth.rmat_scale(scale, 16, seed=8)
+    s1, d1 = synth.rmat_feistel(scale, 0, 16 * n, seed=8)
+    t0, _ = oracle.tc_lcc(n, s0, d0)
+    t1, _ = oracle.tc_lcc(n, s1, d1)
+    fwd = np.arange(n)
+    fwd[np.concatenate([s0, d0])] = np.concatenate([s1, d1])
+    touched = np.zeros(n, dtype=bool)
+    touched[np.concatenate([s0, d0])] = True
+    assert np.array_equal(t1[fwd[touched]], t0[touched])
+    assert t0.sum() == t1.sum()
+
+
 def test_batch_specs_shape():
     specs = synth.batch_specs()
     assert len(specs) == 4096
