@@ -346,7 +346,7 @@ def streamed_bench(ctx, torch, pkg, log_fn, scale: int, ef: int = 16, seed: int 
                        "lcc_equals_host_division": lcc_ok}}
 
 
-def batch_bench(ctx, torch, log_fn, reps: int = 3):
+def batch_bench(ctx, torch, log_fn, reps: int = 3, autotune: bool = True):
     """4096 uneven graphs: a loop of single-graph runs against one batched submission."""
     import numpy as np
     import synth
@@ -375,8 +375,12 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
             g.run(t, l)
         torch.cuda.synchronize()
 
+    submit_s = []
+
     def batched():
+        t0 = time.perf_counter()
         tk = ctx.batch_submit(graphs, tris, lccs)
+        submit_s.append(time.perf_counter() - t0)
         ctx.batch_poll(tk, block=True)
 
     per_graph()
@@ -393,6 +397,17 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
     ref = golden_lines("batch4096_seed7")
     oracle_ok = None if ref is None else result_lines(torch, ms, tris, lccs) == ref
     tl, tb = float(np.median(t_loop)), float(np.median(t_batch))
+    res = {"workload": "4096 graphs, n log-uniform in [64, 16384], half uniform (avg degree 8-32), "
+                       "half R-MAT (EF 8-16), int32 offsets",
+           "graphs": len(specs), "m_total": m_total, "wedges": wedges, "alg_bytes": alg_bytes,
+           "per_graph_ms": tl * 1e3, "batched_ms": tb * 1e3, "speedup": tl / tb,
+           "submit_host_ms": float(np.median(submit_s)) * 1e3,
+           "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same),
+           "matches_oracle_digests": oracle_ok}
+    if not autotune:
+        for g in graphs:
+            g.free()
+        return res
     # the autotuner on the batched launch's knobs, then the same measurement again
     log_fn("[bench] autotuning the batched launch")
     default = ctx.tuning().as_dict()
@@ -411,15 +426,10 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3):
     for g in graphs:
         g.free()
     tt = float(np.median(t_tuned))
-    return {"workload": "4096 graphs, n log-uniform in [64, 16384], half uniform (avg degree 8-32), "
-                        "half R-MAT (EF 8-16), int32 offsets",
-            "graphs": len(specs), "m_total": m_total, "wedges": wedges, "alg_bytes": alg_bytes,
-            "per_graph_ms": tl * 1e3, "batched_ms": tb * 1e3, "speedup": tl / tb,
-            "per_graph_teps": m_total / tl, "batched_teps": m_total / tb, "results_identical": bool(same),
-            "matches_oracle_digests": oracle_ok,
-            "autotuned": {"batch_grab": tuned.batch_grab, "batch_heavy_bits": tuned.batch_heavy_bits,
-                          "batched_ms": tt * 1e3, "speedup": tl / tt, "tuning_seconds": tune_s,
-                          "results_identical": bool(same_tuned)}}
+    res["autotuned"] = {"batch_grab": tuned.batch_grab, "batch_heavy_bits": tuned.batch_heavy_bits,
+                        "batched_ms": tt * 1e3, "speedup": tl / tt, "tuning_seconds": tune_s,
+                        "results_identical": bool(same_tuned)}
+    return res
 
 
 def run_timing(ctx, torch, n, src, dst, offset_bytes, tri, lcc, warm: int = 3, lo: int = 10, hi: int = 200):
@@ -592,6 +602,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-small-graphs comparison")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner in the batch leg")
     ap.add_argument("--no-strategies", action="store_true", help="skip the per-probe-strategy count times")
     ap.add_argument("--no-ext", action="store_true", help="skip the per-edge and directed legs")
     ap.add_argument("--streamed-scale", type=int, default=0,
@@ -716,7 +727,7 @@ def main():
         out["streamed"] = streamed_bench(ctx, torch, pkg, log, args.streamed_scale)
     if not args.no_batch:
         ctx.set_profiling(False)
-        out["batch"] = batch_bench(ctx, torch, log)
+        out["batch"] = batch_bench(ctx, torch, log, autotune=not args.no_autotune)
     if not args.no_serve:
         ctx.set_profiling(False)
         out["serve"] = serve_bench(ctx, torch, log)

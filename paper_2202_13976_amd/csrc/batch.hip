@@ -105,12 +105,14 @@ __device__ __forceinline__ int batch_graph_of_wave(const BatchGraph* __restrict_
     return lo;
 }
 
-// Two phases, as in the single-graph kernel: the heavy vertices of all graphs (those with at
-// least 2^14 probes), one block each (the block's whole LDS is the table), taken one at a
-// time; then all others, one wave each in its slice of the LDS (every vertex of a batched
-// graph fits a slice), taken several at a time (the tuning's batch_grab) when there are plenty.
+// Two kernels, the two phases of the single-graph kernel, launched on two branches of the
+// captured graph so that they run side by side: the heavy vertices of all graphs (those with at
+// least 2^14 probes), one block each (the block's whole LDS is the table), taken one at a time;
+// and all others, one wave each in its slice of the LDS, taken several at a time (the tuning's
+// batch_grab) when there are plenty.  Apart, each kernel is compiled for its own phase only, so
+// the light one keeps fewer registers per lane and more waves resident to hide latency.
 template <typename OffT>
-__global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph* __restrict__ gs, BatchHeader* h,
+__global__ __launch_bounds__(kBatchThreads) void k_batch_heavy(const BatchGraph* __restrict__ gs, BatchHeader* h,
                                                                int which) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int64_t s_item;
@@ -118,9 +120,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t rb = h->region;
     const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
-
-    // the first item of every block and the first grab of every wave are fixed by their
-    // index; only later ones come from the queue counters (atomics on one address serialize)
+    // the first item of every block is fixed by its index; only later ones come from the queue
+    // counter (atomics on one address serialize)
     const int64_t grid = gridDim.x;
     const int64_t hlo = which ? h->heavy4 : 0, hhi = which ? h->heavy : h->heavy4;
     for (int64_t item = hlo + blockIdx.x;;) {
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
         const int32_t v = G.vlist[item - G.heavy_base];
         unsigned long long local = 0;
         process_vertex<OffT, TC_LCC_PROBE_AUTO, kBatchThreads / kWave, true>(a, v, lds, rb * (kBatchThreads / kWave),
-                                                                              threadIdx.x, w, local);
+                                                                              threadIdx.x, w, local, s_tcnt + w * kWave);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
         if (grid >= hhi - hlo) break;
@@ -142,11 +143,22 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_count(const BatchGraph*
         __syncthreads();
     }
 
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kBatchThreads) void k_batch_light(const BatchGraph* __restrict__ gs, BatchHeader* h,
+                                                               int which) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t s_tcnt[kBatchThreads];  // per wave: hits of the 64 tails of a chunk
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t rb = h->region;
+    const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
+    const int64_t grid = gridDim.x;
     uint8_t* region = lds + (size_t)w * rb;
     const int64_t lo = which ? h->light4 : 0, hi = which ? h->light : h->light4;
     const int64_t waves = grid * (kBatchThreads / kWave);
     // light grabs: several items when there are plenty per wave, single ones when few; the
-    // fixed first grabs go to the last blocks first, which hold no heavy vertex
+    // first grab of every wave is fixed by its index
     const int grab = (hi - lo) >= waves * (int64_t)h->grab * 4 ? h->grab : 1;
     for (int64_t item = lo + ((grid - 1 - blockIdx.x) * (int64_t)(kBatchThreads / kWave) + w) * grab;;) {
         if (item >= hi) break;
@@ -272,7 +284,20 @@ struct Slot {
     size_t cap_done = 0;
     // captured launches, keyed by (region class, which kernels)
     std::map<uint64_t, hipGraphExec_t> execs;
+    // the heavy kernels' branch of the captured graph
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
+
+hipError_t slot_streams(Slot& s) {
+    hipError_t e = hipSuccess;
+    if (!s.stream && e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+    if (!s.ev && e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
+    if (!s.side && e == hipSuccess) e = hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking);
+    if (!s.fork && e == hipSuccess) e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming);
+    if (!s.join && e == hipSuccess) e = hipEventCreateWithFlags(&s.join, hipEventDisableTiming);
+    return e;
+}
 
 struct Engine {
     Slot slots[kBatchSlots];
@@ -408,22 +433,37 @@ tc_lcc_status capture(Slot& s, uint32_t region, bool has4, bool has8, int gclass
         return TC_LCC_OK;
     }
     const size_t lds = (size_t)region * (kBatchThreads / kWave);
-    int per4 = 0, per8 = 0;
-    TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per4, k_batch_count<int32_t>, kBatchThreads, lds));
-    TCL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per8, k_batch_count<int64_t>, kBatchThreads, lds));
-    unsigned g4 = (unsigned)(cu_count * std::max(per4, 1));
-    unsigned g8 = (unsigned)(cu_count * std::max(per8, 1));
-    if (gclass < kNumGridClasses) {
-        g4 = std::min(g4, kGridClasses[gclass]);
-        g8 = std::min(g8, kGridClasses[gclass]);
-    }
-    const unsigned ge = std::min(std::max(g4, g8), 1024u);
+    // blocks of each kernel: what the GPU holds of it alone, or the grid class of a small batch
+    auto grid = [&](const void* kern) -> unsigned {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBatchThreads, lds) != hipSuccess) {
+            (void)hipGetLastError();
+            per = 1;
+        }
+        unsigned gsz = (unsigned)(cu_count * std::max(per, 1));
+        if (gclass < kNumGridClasses) gsz = std::min(gsz, kGridClasses[gclass]);
+        return gsz;
+    };
+    const unsigned h4 = grid((const void*)k_batch_heavy<int32_t>), l4 = grid((const void*)k_batch_light<int32_t>);
+    const unsigned h8 = grid((const void*)k_batch_heavy<int64_t>), l8 = grid((const void*)k_batch_light<int64_t>);
+    const unsigned ge = std::min(std::max(l4, l8), 1024u);
     hipGraph_t graph = nullptr;
     TCL_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-    if (has4) k_batch_count<int32_t><<<g4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
-    if (has8) k_batch_count<int64_t><<<g8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
-    k_batch_epilogue<<<ge, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
-    hipError_t e = hipStreamEndCapture(s.stream, &graph);
+    // the heavy kernels on a side branch (fork and join through events), the light ones here
+    hipError_t e = hipEventRecord(s.fork, s.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s.side, s.fork, 0);
+    if (e == hipSuccess) {
+        if (has4) k_batch_heavy<int32_t><<<h4, kBatchThreads, lds, s.side>>>(s.d_graphs, s.d_hdr, 0);
+        if (has8) k_batch_heavy<int64_t><<<h8, kBatchThreads, lds, s.side>>>(s.d_graphs, s.d_hdr, 1);
+        if (has4) k_batch_light<int32_t><<<l4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
+        if (has8) k_batch_light<int64_t><<<l8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
+        e = hipEventRecord(s.join, s.side);
+    }
+    if (e == hipSuccess) e = hipStreamWaitEvent(s.stream, s.join, 0);
+    if (e == hipSuccess) k_batch_epilogue<<<ge, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
+    hipError_t ec = hipStreamEndCapture(s.stream, &graph);
+    if (e == hipSuccess) e = ec;
+    else if (graph) (void)hipGraphDestroy(graph), graph = nullptr;
     if (e != hipSuccess) {
         set_error("batch: stream capture failed: %s", hipGetErrorString(e));
         return TC_LCC_DEVICE_ERROR;
@@ -484,8 +524,12 @@ void batch_engine_destroy(tc_lcc_ctx ctx) {
         if (s.h_graphs) (void)hipHostFree(s.h_graphs);
         if (s.h_hdr) (void)hipHostFree(s.h_hdr);
         if (s.h_done) (void)hipHostFree(s.h_done);
+        if (s.side) (void)hipStreamSynchronize(s.side);
         if (s.ev) (void)hipEventDestroy(s.ev);
+        if (s.fork) (void)hipEventDestroy(s.fork);
+        if (s.join) (void)hipEventDestroy(s.join);
         if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.side) (void)hipStreamDestroy(s.side);
     }
     delete e;
     ctx->batch = nullptr;
@@ -518,10 +562,7 @@ tc_lcc_status tcl::batch_reserve(tc_lcc_ctx ctx, size_t graphs) {
     std::lock_guard<std::mutex> lk(e->mu);
     for (Slot& s : e->slots) {
         if (s.busy) continue;
-        if (!s.stream) {
-            TCL_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
-            TCL_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
-        }
+        TCL_HIP(slot_streams(s));
         tc_lcc_status st = ensure_capacity(ctx, s, std::max<size_t>(graphs, 1), std::max<size_t>(graphs, 1), 1);
         if (st != TC_LCC_OK) return st;
     }
@@ -567,10 +608,7 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
         ctx->tickets_inflight--;
         s = oldest;
     }
-    if (!s->stream) {
-        TCL_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
-        TCL_HIP(hipEventCreateWithFlags(&s->ev, hipEventDisableTiming));
-    }
+    TCL_HIP(slot_streams(*s));
 
     // order: 4-byte-offset graphs first, then 8-byte ones; directed graphs and graphs with lists
     // longer than the single-graph launch's hash (which that launch takes as a sorted list in

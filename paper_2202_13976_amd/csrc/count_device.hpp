@@ -221,7 +221,7 @@ __device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a
 // found here is a triangle with v as its middle vertex, so the hits are also v's share
 // (`local`).
 template <typename OffT, int MODE, int NWAVES>
-__device__ void walk_tails(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb, int wig,
+__device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb, int wig,
                            unsigned long long& local) {
     constexpr int kRing = 2 * kUnroll;
     const int lane = lane_id();
@@ -465,24 +465,33 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
     }
 }
 
-// One wave over the tails of v's in-edges with windows that cross tail boundaries: for graphs
-// whose tails are short (the many-small-graphs batch: a dozen candidates per tail), a window of
-// one tail would leave most of the 64 lanes idle.  Per chunk of 64 in-edges, lane k holds
-// in-edge k; the tails are laid end to end (exclusive prefix sums of their lengths) and every
-// window takes the next 64 candidates of that sequence.  Lane i finds the tail of its candidate
-// by a binary search over the lanes' prefix sums (lane shuffles), reads the candidate, probes
-// it, and counts a hit at its entry of N+(v) and in its tail's LDS counter (tcnt: 64 words of
-// this wave); the tails' counts go to t(u) once the chunk is done.
-template <typename OffT, int MODE>
-__device__ void walk_flat(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb, uint32_t* tcnt,
-                          unsigned long long& local) {
+// The waves of a group over the tails of v's in-edges with windows that cross tail boundaries:
+// for graphs whose tails are short (the many-small-graphs batch: a dozen candidates per tail),
+// a window of one tail would leave most of the 64 lanes idle.  Wave wig takes every NWAVES-th
+// in-edge, 64 at a time (a chunk: lane k holds its k-th in-edge, as first_in_edges loads it);
+// the chunk's tails are laid end to end (exclusive prefix sums of their lengths) and every
+// window takes the next 64 candidates of that sequence.  Lane i finds the tail of its
+// candidate by a binary search over the lanes' prefix sums (lane shuffles); kFlatRound windows
+// are formed and their candidates loaded before any is probed, so that many loads are in flight
+// per wave.  A hit is counted at its entry of N+(v) (or, searching N+(v) in HBM, added to t(w)
+// at once); the hits of one tail in one window are summed by a popcount over that tail's lanes
+// and added to the tail's LDS counter (tcnt: 64 words of this wave) by its last lane; the
+// tails' counts go to t(u) once the chunk is done.
+constexpr int kFlatRound = 4;
+
+template <typename OffT, int MODE, int NWAVES = 1>
+__device__ __forceinline__ void walk_flat(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb,
+                                          uint32_t* tcnt, int wig, unsigned long long& local) {
     const int lane = lane_id();
+    wig = __builtin_amdgcn_readfirstlane(wig);
     const OffT i0 = ie.i0, i1 = ie.i1;
+    constexpr OffT kSpan = (OffT)kWave * NWAVES;
     int32_t u = ie.u, len = ie.len;
     OffT st = ie.st;
-    for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
+    const unsigned long long le = lanemask_lt() | (1ull << lane);
+    for (OffT cb = i0; cb < i1; cb += kSpan) {
         if (cb != i0) {
-            const OffT k = cb + (OffT)lane;
+            const OffT k = cb + (OffT)lane * NWAVES + wig;
             u = 0;
             st = 0;
             len = 0;
@@ -491,41 +500,69 @@ __device__ void walk_flat(const CountArgs<OffT>& a, const InEdges<OffT>& ie, con
         const int32_t incl = wave_inclusive_scan(len);
         const int32_t excl = incl - len;
         const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+        // candidate c of tail k lies at adj[st_k + (c - excl_k)] = adj[dk + c]
+        const OffT dk = st - (OffT)excl;
         tcnt[lane] = 0u;
         wave_lds_sync();
-        for (int32_t base = 0; base < total; base += kWave) {
-            const int32_t c = base + lane;
-            const bool valid = c < total;
-            // last tail k whose first candidate is at or before c (tails are nonempty)
-            int k = 0;
+        for (int32_t base = 0; base < total; base += kWave * kFlatRound) {
+            int32_t xs[kFlatRound], ks[kFlatRound];
+            bool vs[kFlatRound];
 #pragma unroll
-            for (int step = kWave / 2; step >= 1; step >>= 1) {
-                const int probe = k + step;
-                const int32_t e = __shfl(excl, probe < kWave ? probe : kWave - 1, kWave);
-                if (probe < kWave && e <= c) k = probe;
+            for (int r = 0; r < kFlatRound; ++r) {
+                const int32_t c = base + r * kWave + lane;
+                vs[r] = c < total;
+                ks[r] = 0;
+                xs[r] = 0;
+                if (base + r * kWave < total) {  // wave-uniform
+                    // last tail k whose first candidate is at or before c (tails are nonempty)
+                    int k = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step >= 1; step >>= 1) {
+                        const int probe = k + step;
+                        const int32_t e = __shfl(excl, probe < kWave ? probe : kWave - 1, kWave);
+                        if (probe < kWave && e <= c) k = probe;
+                    }
+                    ks[r] = k;
+                    OffT d;
+                    if constexpr (sizeof(OffT) == 8) {
+                        const uint64_t d64 = (uint64_t)dk;
+                        d = (OffT)((uint64_t)(uint32_t)__shfl((int32_t)(uint32_t)d64, k, kWave) |
+                                   ((uint64_t)(uint32_t)__shfl((int32_t)(uint32_t)(d64 >> 32), k, kWave) << 32));
+                    } else {
+                        d = (OffT)__shfl((int32_t)dk, k, kWave);
+                    }
+                    if (vs[r]) xs[r] = a.adj[d + (OffT)c];
+                }
             }
-            const int32_t ek = __shfl(excl, k, kWave);
-            OffT sk;
-            if constexpr (sizeof(OffT) == 8) {
-                const uint64_t s64 = (uint64_t)st;
-                sk = (OffT)((uint64_t)(uint32_t)__shfl((int32_t)(uint32_t)s64, k, kWave) |
-                            ((uint64_t)(uint32_t)__shfl((int32_t)(uint32_t)(s64 >> 32), k, kWave) << 32));
-            } else {
-                sk = (OffT)__shfl((int32_t)st, k, kWave);
+#pragma unroll
+            for (int r = 0; r < kFlatRound; ++r) {
+                if (base + r * kWave >= total) break;  // wave-uniform
+                const int32_t x = xs[r];
+                const int k = ks[r];
+                bool hit;
+                if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
+                    const uint32_t ii = (uint32_t)(x - tb.base);  // candidates are ranks above v
+                    const uint32_t wi = min(ii >> 5, tb.words);   // beyond the range: the zero guard word
+                    const uint2 e = *reinterpret_cast<const uint2*>(tb.bm + 2 * wi);
+                    hit = vs[r] && __builtin_amdgcn_ubfe(e.x, ii, 1u) != 0u;
+                    if (hit) atomicAdd(&tb.cnt[e.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(e.x, 0u, ii))], 1u);
+                } else {
+                    hit = probe_one<MODE>(tb, x, vs[r]);
+                }
+                local += hit ? 1ull : 0ull;
+                // hits per tail: the lanes of one tail are contiguous; the last lane of each run
+                // adds the run's hits (one LDS add per tail and window)
+                const unsigned long long H = __builtin_amdgcn_ballot_w64(hit);
+                const int kp = __shfl_up(k, 1, kWave);
+                const int kn = __shfl_down(k, 1, kWave);
+                const unsigned long long heads = __builtin_amdgcn_ballot_w64(lane == 0 || kp != k);
+                const bool last = vs[r] && (lane == kWave - 1 || kn != k || base + r * kWave + lane + 1 >= total);
+                if (last) {
+                    const int start = 63 - __clzll(heads & le);
+                    const uint32_t cnt = (uint32_t)__popcll(H & le & ~((1ull << start) - 1ull));
+                    if (cnt) atomicAdd(&tcnt[k], cnt);
+                }
             }
-            const int32_t x = a.adj[sk + (OffT)(valid ? c - ek : 0)];
-            bool hit;
-            if constexpr (MODE == TC_LCC_PROBE_BITMAP) {
-                const uint32_t ii = (uint32_t)(x - tb.base);  // candidates are ranks above v
-                const uint32_t wi = min(ii >> 5, tb.words);   // beyond the range: the zero guard word
-                const uint2 e = *reinterpret_cast<const uint2*>(tb.bm + 2 * wi);
-                hit = valid && __builtin_amdgcn_ubfe(e.x, ii, 1u) != 0u;
-                if (hit) atomicAdd(&tb.cnt[e.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(e.x, 0u, ii))], 1u);
-            } else {
-                hit = probe_one<MODE>(tb, x, valid);
-            }
-            if (hit) atomicAdd(&tcnt[k], 1u);
-            local += hit ? 1ull : 0ull;
         }
         wave_lds_sync();
         const uint32_t mine = tcnt[lane];
@@ -558,11 +595,10 @@ __device__ __forceinline__ VertexHead<OffT> vertex_head(const CountArgs<OffT>& a
 
 // FALLBACK (the batched kernel): a vertex whose bucket hash does not fit the region either is
 // searched in N+(v) where it lies in HBM (each hit added to t(w) at once), so a graph whose
-// largest lists exceed a batched slice still runs in the batch.
-// tcnt (the batched kernel's light vertices, NWAVES == 1): 64 LDS words of this wave; the bitmap
-// and hash probes then take windows across tail boundaries (walk_flat).
+// largest lists exceed a batched slice still runs in the batch; and every probe takes windows
+// across tail boundaries (walk_flat), with tcnt the 64 LDS words of this wave.
 template <typename OffT, int PROBE, int NWAVES, bool FALLBACK = false>
-__device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>& hd, uint8_t* region,
+__device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>& hd, uint8_t* region,
                                uint32_t region_bytes, int gtid, int wig, unsigned long long& local,
                                uint32_t* tcnt = nullptr) {
     constexpr int gsize = NWAVES * kWave;
@@ -593,7 +629,7 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
     }
     if constexpr (FALLBACK) {
         if (mode == kProbeGlobal) {
-            walk_tails<OffT, kProbeGlobal, NWAVES>(a, ie, tb, wig, local);
+            walk_flat<OffT, kProbeGlobal, NWAVES>(a, ie, tb, tcnt, wig, local);
             group_sync<NWAVES>();
             return;
         }
@@ -638,15 +674,15 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
     group_sync<NWAVES>();
 
     // ---- probe the tails of the in-edges
-    if (NWAVES == 1 && FALLBACK && tcnt && (mode == TC_LCC_PROBE_BITMAP || mode == TC_LCC_PROBE_HASH)) {
-        if constexpr (NWAVES == 1 && FALLBACK) {
-            if (mode == TC_LCC_PROBE_BITMAP) walk_flat<OffT, TC_LCC_PROBE_BITMAP>(a, ie, tb, tcnt, local);
-            else walk_flat<OffT, TC_LCC_PROBE_HASH>(a, ie, tb, tcnt, local);
-        }
-    } else if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, wig, local);
-    else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, wig, local);
-    else if (mode == TC_LCC_PROBE_MERGE) walk_tails_hybrid<OffT, NWAVES>(a, v, tb, wig, local);
-    else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, ie, tb, wig, local);
+    if constexpr (FALLBACK) {
+        if (mode == TC_LCC_PROBE_BITMAP) walk_flat<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, tcnt, wig, local);
+        else walk_flat<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, tcnt, wig, local);
+    } else {
+        if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, wig, local);
+        else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, wig, local);
+        else if (mode == TC_LCC_PROBE_MERGE) walk_tails_hybrid<OffT, NWAVES>(a, v, tb, wig, local);
+        else walk_tails<OffT, TC_LCC_PROBE_SORTED, NWAVES>(a, ie, tb, wig, local);
+    }
     group_sync<NWAVES>();
 
     // ---- flush the per-entry counters of N+(v)
@@ -669,8 +705,9 @@ __device__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>&
 
 template <typename OffT, int PROBE, int NWAVES, bool FALLBACK = false>
 __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, int32_t v, uint8_t* region,
-                                               uint32_t region_bytes, int gtid, int wig, unsigned long long& local) {
-    process_vertex<OffT, PROBE, NWAVES, FALLBACK>(a, vertex_head(a, v), region, region_bytes, gtid, wig, local);
+                                               uint32_t region_bytes, int gtid, int wig, unsigned long long& local,
+                                               uint32_t* tcnt = nullptr) {
+    process_vertex<OffT, PROBE, NWAVES, FALLBACK>(a, vertex_head(a, v), region, region_bytes, gtid, wig, local, tcnt);
 }
 
 }  // namespace tcl
