@@ -346,7 +346,7 @@ def streamed_bench(ctx, torch, pkg, log_fn, scale: int, ef: int = 16, seed: int 
                        "lcc_equals_host_division": lcc_ok}}
 
 
-def batch_bench(ctx, torch, log_fn, reps: int = 3, autotune: bool = True):
+def batch_bench(ctx, torch, pkg, log_fn, reps: int = 3, autotune: bool = True):
     """4096 uneven graphs: a loop of single-graph runs against one batched submission."""
     import numpy as np
     import synth
@@ -376,10 +376,11 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3, autotune: bool = True):
         torch.cuda.synchronize()
 
     submit_s = []
+    bargs = pkg.BatchArgs(graphs, tris, lccs)
 
     def batched():
         t0 = time.perf_counter()
-        tk = ctx.batch_submit(graphs, tris, lccs)
+        tk = ctx.batch_submit(bargs)
         submit_s.append(time.perf_counter() - t0)
         ctx.batch_poll(tk, block=True)
 
@@ -416,6 +417,7 @@ def batch_bench(ctx, torch, log_fn, reps: int = 3, autotune: bool = True):
     tune_s = time.perf_counter() - t0
     for t in tris:
         t.fill_(-1)
+    torch.cuda.synchronize()  # the batch runs on the library's streams, not ordered after torch's
     t_tuned = []
     for _ in range(reps):
         t0 = time.perf_counter()
@@ -727,7 +729,7 @@ def main():
         out["streamed"] = streamed_bench(ctx, torch, pkg, log, args.streamed_scale)
     if not args.no_batch:
         ctx.set_profiling(False)
-        out["batch"] = batch_bench(ctx, torch, log, autotune=not args.no_autotune)
+        out["batch"] = batch_bench(ctx, torch, pkg, log, autotune=not args.no_autotune)
     if not args.no_serve:
         ctx.set_profiling(False)
         out["serve"] = serve_bench(ctx, torch, log)

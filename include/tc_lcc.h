@@ -244,9 +244,10 @@ tc_lcc_status tc_lcc_batch_poll(tc_lcc_ctx ctx, tc_lcc_ticket t, int block, int*
  * done: host array of count bytes (count = the graphs of the submission); done[i]
  * becomes 1 once graph i's outputs are written, which work issued afterwards on any
  * stream of the device observes.  Graphs counted together in the persistent launch
- * finish together; graphs that take the single-graph launches (id ranges whose
- * tables do not fit LDS) run after it, least work first, and each finishes on its
- * own.  Does not wait and does not release the ticket.  INVALID_ARGUMENT for an
+ * finish together; graphs that take the single-graph launches (directed graphs, compact
+ * reverse lists, lists beyond a block's hash, or at least 2^25 probes: enough work to fill the
+ * GPU alone, which the single-graph kernel with its larger tables does faster) run after it,
+ * least work first, and each finishes on its own.  Does not wait and does not release the ticket.  INVALID_ARGUMENT for an
  * unknown ticket or a count that differs from the submission's. */
 tc_lcc_status tc_lcc_batch_progress(tc_lcc_ctx ctx, tc_lcc_ticket t, int count, uint8_t* done);
 
@@ -263,8 +264,7 @@ tc_lcc_status tc_lcc_batch_progress(tc_lcc_ctx ctx, tc_lcc_ticket t, int count, 
  * A batched request takes its graph's counters (8 bytes per vertex) first-fit
  * from the arena and returns them, zeroed again by the epilogue, as soon as its own graph
  * is done (tc_lcc_batch_progress), not when its whole batch is; a request whose graph takes
- * the single-graph launches (directed, or lists beyond a block's hash) uses the graph's own
- * counters.  OVER_BUDGET from create if the arena cannot be had within the context's budget.
+ * the single-graph launches (see tc_lcc_batch_progress) uses the graph's own counters.  OVER_BUDGET from create if the arena cannot be had within the context's budget.
  * max_inflight = max_batch = 1 gives the plain path: one request at a time through
  * tc_lcc_run (its budget then bounds 8 bytes per vertex of the request in flight).  Results
  * are identical to tc_lcc_run's for every request. */

@@ -231,6 +231,24 @@ class Graph:
             pass
 
 
+class BatchArgs:
+    """The pointer arrays of one batch (graph handles, output pointers), built once: a batch that is
+    submitted many times need not marshal thousands of pointers each time.  Keeps the graphs and
+    outputs alive while it exists."""
+
+    def __init__(self, graphs, tris, lccs=None):
+        count = len(graphs)
+        self.count = count
+        # built by numpy from the handles and data pointers (a ctypes array built from a list of
+        # Python ints costs about twice as much for thousands of graphs)
+        self.gh = np.fromiter(((g.handle.value or 0) if g.handle else 0 for g in graphs), dtype=np.uint64,
+                              count=count)
+        self.th = np.fromiter((t.data_ptr() for t in tris), dtype=np.uint64, count=count)
+        self.lh = np.fromiter(((l.data_ptr() if l is not None else 0) for l in (lccs or [None] * count)),
+                              dtype=np.uint64, count=count)
+        self._keep = (list(graphs), list(tris), list(lccs) if lccs else None)
+
+
 class Context:
     """One GPU: memory pool with an optional HBM budget, tuning, batch queues (tc_lcc_ctx)."""
 
@@ -316,16 +334,12 @@ class Context:
         succeed, the one after fails; a negative value turns it off."""
         _check(lib().tc_lcc_debug_fail_alloc(self.handle, after), "tc_lcc_debug_fail_alloc")
 
-    def batch_submit(self, graphs, tris, lccs=None) -> int:
-        count = len(graphs)
-        # pointer arrays built by numpy from the handles and data pointers (a ctypes array built
-        # from a list of Python ints costs about twice as much for thousands of graphs)
-        gh = np.fromiter(((g.handle.value or 0) if g.handle else 0 for g in graphs), dtype=np.uint64, count=count)
-        th = np.fromiter((t.data_ptr() for t in tris), dtype=np.uint64, count=count)
-        lh = np.fromiter(((l.data_ptr() if l is not None else 0) for l in (lccs or [None] * count)),
-                         dtype=np.uint64, count=count)
+    def batch_submit(self, graphs, tris=None, lccs=None) -> int:
+        """tc_lcc_batch_submit: `graphs` with their outputs `tris` (and `lccs`), or a BatchArgs
+        built once for repeated submissions of the same batch."""
+        a = graphs if isinstance(graphs, BatchArgs) else BatchArgs(graphs, tris, lccs)
         tk = ctypes.c_uint64()
-        _check(lib().tc_lcc_batch_submit(self.handle, count, gh.ctypes.data, th.ctypes.data, lh.ctypes.data,
+        _check(lib().tc_lcc_batch_submit(self.handle, a.count, a.gh.ctypes.data, a.th.ctypes.data, a.lh.ctypes.data,
                                          ctypes.byref(tk)), "tc_lcc_batch_submit")
         return int(tk.value)
 

@@ -48,7 +48,7 @@ struct BatchGraph {
     int64_t chunk_base; // first epilogue chunk of the graph in the batch
     int32_t index;      // position of the graph in the submission (its done flag)
     int32_t nchunks;    // epilogue chunks of the graph
-    unsigned int chunks_done;  // epilogue chunks finished (0 in every submission)
+    int32_t pad_chunks;
     uint32_t pad_;
 };
 
@@ -105,12 +105,12 @@ __device__ __forceinline__ int batch_graph_of_wave(const BatchGraph* __restrict_
     return lo;
 }
 
-// Two kernels, the two phases of the single-graph kernel, launched on two branches of the
-// captured graph so that they run side by side: the heavy vertices of all graphs (those with at
-// least 2^14 probes), one block each (the block's whole LDS is the table), taken one at a time;
-// and all others, one wave each in its slice of the LDS, taken several at a time (the tuning's
-// batch_grab) when there are plenty.  Apart, each kernel is compiled for its own phase only, so
-// the light one keeps fewer registers per lane and more waves resident to hide latency.
+// Two kernels, the two phases of the single-graph kernel, one after the other in the captured
+// graph: the heavy vertices of all graphs (those with at least 2^14 probes), one block each (the
+// block's whole LDS is the table), taken one at a time; then all others, one wave each in its
+// slice of the LDS, taken several at a time (the tuning's batch_grab) when there are plenty.
+// Apart, each kernel is compiled for its own phase only, so the light one keeps fewer registers
+// per lane and more waves resident to hide latency.
 template <typename OffT>
 __global__ __launch_bounds__(kBatchThreads) void k_batch_heavy(const BatchGraph* __restrict__ gs, BatchHeader* h,
                                                                int which) {
@@ -199,15 +199,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_light(const BatchGraph*
 }
 
 // Eq. 2 per vertex, as the single-graph epilogue, over chunks of kEpiChunk vertices of all
-// graphs; each counter is reset to zero once read.  A graph's done flag goes up when its
-// last chunk is finished: every wave first waits for its own stores, the block's first
-// thread then makes them visible device-wide and counts the chunk; the thread that counts
-// the last chunk makes everything visible to the host and raises the flag.
-__global__ __launch_bounds__(256) void k_batch_epilogue(BatchGraph* __restrict__ gs, const BatchHeader* h,
-                                                        unsigned int* __restrict__ done) {
+// graphs; each counter is reset to zero once read.
+__global__ __launch_bounds__(256) void k_batch_epilogue(const BatchGraph* __restrict__ gs, const BatchHeader* h) {
     const int count = h->count;
     const int64_t chunks = h->chunks;
-    const unsigned int seq = h->seq;
     for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
         int ga = 0, gb = count - 1;  // last graph with chunk_base <= c
         while (ga < gb) {
@@ -231,19 +226,19 @@ __global__ __launch_bounds__(256) void k_batch_epilogue(BatchGraph* __restrict__
                 G.lcc[v] = x;
             }
         }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached L2
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            const unsigned int prev =
-                __hip_atomic_fetch_add(&gs[g].chunks_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev + 1 == (unsigned int)G.nchunks) {
-                __threadfence_system();
-                done[G.index] = seq;
-            }
-        }
-        __syncthreads();
     }
+}
+
+// The done flags of the batched graphs, after the epilogue kernel has finished (its results are
+// then visible on the whole device): a system-wide fence, so that the host sees a flag only
+// after what precedes it, then one flag per graph.  One fence per batch instead of one per graph.
+__global__ __launch_bounds__(256) void k_batch_flags(const BatchGraph* __restrict__ gs, const BatchHeader* h,
+                                                     unsigned int* __restrict__ done) {
+    const int count = h->count;
+    const unsigned int seq = h->seq;
+    __threadfence_system();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        done[gs[i].index] = seq;
 }
 
 __global__ void k_batch_clear(unsigned long long* __restrict__ p, size_t n) {
@@ -284,18 +279,12 @@ struct Slot {
     size_t cap_done = 0;
     // captured launches, keyed by (region class, which kernels)
     std::map<uint64_t, hipGraphExec_t> execs;
-    // the heavy kernels' branch of the captured graph
-    hipStream_t side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 hipError_t slot_streams(Slot& s) {
     hipError_t e = hipSuccess;
     if (!s.stream && e == hipSuccess) e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
     if (!s.ev && e == hipSuccess) e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
-    if (!s.side && e == hipSuccess) e = hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking);
-    if (!s.fork && e == hipSuccess) e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming);
-    if (!s.join && e == hipSuccess) e = hipEventCreateWithFlags(&s.join, hipEventDisableTiming);
     return e;
 }
 
@@ -449,21 +438,15 @@ tc_lcc_status capture(Slot& s, uint32_t region, bool has4, bool has8, int gclass
     const unsigned ge = std::min(std::max(l4, l8), 1024u);
     hipGraph_t graph = nullptr;
     TCL_HIP(hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal));
-    // the heavy kernels on a side branch (fork and join through events), the light ones here
-    hipError_t e = hipEventRecord(s.fork, s.stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s.side, s.fork, 0);
-    if (e == hipSuccess) {
-        if (has4) k_batch_heavy<int32_t><<<h4, kBatchThreads, lds, s.side>>>(s.d_graphs, s.d_hdr, 0);
-        if (has8) k_batch_heavy<int64_t><<<h8, kBatchThreads, lds, s.side>>>(s.d_graphs, s.d_hdr, 1);
-        if (has4) k_batch_light<int32_t><<<l4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
-        if (has8) k_batch_light<int64_t><<<l8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
-        e = hipEventRecord(s.join, s.side);
-    }
-    if (e == hipSuccess) e = hipStreamWaitEvent(s.stream, s.join, 0);
-    if (e == hipSuccess) k_batch_epilogue<<<ge, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
-    hipError_t ec = hipStreamEndCapture(s.stream, &graph);
-    if (e == hipSuccess) e = ec;
-    else if (graph) (void)hipGraphDestroy(graph), graph = nullptr;
+    // heavy vertices first, each kernel with the whole GPU (heaviest first, so the heavy phase
+    // ends on short items), then the light ones
+    if (has4) k_batch_heavy<int32_t><<<h4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
+    if (has8) k_batch_heavy<int64_t><<<h8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
+    if (has4) k_batch_light<int32_t><<<l4, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 0);
+    if (has8) k_batch_light<int64_t><<<l8, kBatchThreads, lds, s.stream>>>(s.d_graphs, s.d_hdr, 1);
+    k_batch_epilogue<<<ge, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr);
+    k_batch_flags<<<1, 256, 0, s.stream>>>(s.d_graphs, s.d_hdr, s.d_done);
+    hipError_t e = hipStreamEndCapture(s.stream, &graph);
     if (e != hipSuccess) {
         set_error("batch: stream capture failed: %s", hipGetErrorString(e));
         return TC_LCC_DEVICE_ERROR;
@@ -524,12 +507,8 @@ void batch_engine_destroy(tc_lcc_ctx ctx) {
         if (s.h_graphs) (void)hipHostFree(s.h_graphs);
         if (s.h_hdr) (void)hipHostFree(s.h_hdr);
         if (s.h_done) (void)hipHostFree(s.h_done);
-        if (s.side) (void)hipStreamSynchronize(s.side);
         if (s.ev) (void)hipEventDestroy(s.ev);
-        if (s.fork) (void)hipEventDestroy(s.fork);
-        if (s.join) (void)hipEventDestroy(s.join);
         if (s.stream) (void)hipStreamDestroy(s.stream);
-        if (s.side) (void)hipStreamDestroy(s.side);
     }
     delete e;
     ctx->batch = nullptr;
@@ -551,9 +530,19 @@ struct Plan {
 
 }  // namespace
 
+// A graph that takes the single-graph launches: directed, compact reverse lists, lists beyond a
+// block's hash, or enough work to fill the GPU alone (the single-graph kernel's wave slices and
+// block tables are larger than a batched slice, so fewer of its vertices search HBM; a batch
+// pays only for graphs too small to fill the GPU).
+constexpr uint64_t kSoloWedges = 1ull << 25;
+
+static bool solo_graph(const GraphDev& d) {
+    return d.directed || d.compact || d.n_global > 0 || d.n_list > 0 || d.wedges >= kSoloWedges;
+}
+
 bool tcl::batch_graph_solo(tc_lcc_graph g) {
     std::lock_guard<std::mutex> gl(g->mu);
-    return g->d.directed || g->d.compact || g->d.n_global > 0 || g->d.n_list > 0;
+    return solo_graph(g->d);
 }
 
 tc_lcc_status tcl::batch_reserve(tc_lcc_ctx ctx, size_t graphs) {
@@ -624,7 +613,7 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
         const GraphDev& d = g->d;
         const uint32_t r = region_need(d);
         Plan& p = plan[(size_t)i];
-        if (d.directed || d.compact || d.n_global > 0 || d.n_list > 0) {
+        if (solo_graph(d)) {
             p.solo = true;
             solo.push_back(i);
             continue;
@@ -699,7 +688,7 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
             b.chunk_base = chunk;
             b.index = i;
             b.nchunks = (int32_t)std::max<int64_t>(1, (d.n + kEpiChunk - 1) / kEpiChunk);  // an empty graph still gets its flag
-            b.chunks_done = 0;
+            b.pad_chunks = 0;
             b.pad_ = 0;
             heavy += b.heavy;
             light += b.light;

@@ -593,10 +593,11 @@ __device__ __forceinline__ VertexHead<OffT> vertex_head(const CountArgs<OffT>& a
     return VertexHead<OffT>{v, a.out_off[v], a.out_off[v + 1], a.in_off[v], a.in_off[v + 1]};
 }
 
-// FALLBACK (the batched kernel): a vertex whose bucket hash does not fit the region either is
+// FALLBACK (the batched kernels): a vertex whose bucket hash does not fit the region either is
 // searched in N+(v) where it lies in HBM (each hit added to t(w) at once), so a graph whose
-// largest lists exceed a batched slice still runs in the batch; and every probe takes windows
-// across tail boundaries (walk_flat), with tcnt the 64 LDS words of this wave.
+// largest lists exceed a batched slice still runs in the batch; and a vertex of one wave (the
+// light ones: short tails) takes windows across tail boundaries (walk_flat), with tcnt the 64
+// LDS words of this wave.  A heavy vertex keeps the per-tail windows with their ring of loads.
 template <typename OffT, int PROBE, int NWAVES, bool FALLBACK = false>
 __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const VertexHead<OffT>& hd, uint8_t* region,
                                uint32_t region_bytes, int gtid, int wig, unsigned long long& local,
@@ -629,7 +630,8 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const V
     }
     if constexpr (FALLBACK) {
         if (mode == kProbeGlobal) {
-            walk_flat<OffT, kProbeGlobal, NWAVES>(a, ie, tb, tcnt, wig, local);
+            if constexpr (NWAVES == 1) walk_flat<OffT, kProbeGlobal, 1>(a, ie, tb, tcnt, wig, local);
+            else walk_tails<OffT, kProbeGlobal, NWAVES>(a, ie, tb, wig, local);
             group_sync<NWAVES>();
             return;
         }
@@ -674,9 +676,9 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const V
     group_sync<NWAVES>();
 
     // ---- probe the tails of the in-edges
-    if constexpr (FALLBACK) {
-        if (mode == TC_LCC_PROBE_BITMAP) walk_flat<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, tcnt, wig, local);
-        else walk_flat<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, tcnt, wig, local);
+    if constexpr (FALLBACK && NWAVES == 1) {
+        if (mode == TC_LCC_PROBE_BITMAP) walk_flat<OffT, TC_LCC_PROBE_BITMAP, 1>(a, ie, tb, tcnt, wig, local);
+        else walk_flat<OffT, TC_LCC_PROBE_HASH, 1>(a, ie, tb, tcnt, wig, local);
     } else {
         if (mode == TC_LCC_PROBE_BITMAP) walk_tails<OffT, TC_LCC_PROBE_BITMAP, NWAVES>(a, ie, tb, wig, local);
         else if (mode == TC_LCC_PROBE_HASH) walk_tails<OffT, TC_LCC_PROBE_HASH, NWAVES>(a, ie, tb, wig, local);

@@ -9,7 +9,8 @@ namespace tcl {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte access
 
 constexpr int kCopyThreads = 256;
-constexpr int kCopyVec = 4;  // 16-byte vectors per thread and step, all loaded before any store
+constexpr int kCopyVec = 1;  // 16-byte vectors per thread and step, all loaded before any store
+constexpr int kCopyBlocksPerCu = 4;
 
 __global__ __launch_bounds__(kCopyThreads) void k_hbm_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                                            size_t n16) {
@@ -39,9 +40,11 @@ extern "C" tc_lcc_status tc_lcc_hbm_copy(const void* src, void* dst, uint64_t by
     TCL_HIP(hipGetDevice(&dev));
     TCL_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t n16 = bytes / 16;
-    // 8 blocks per compute unit: enough loads in flight to cover HBM latency
+    // 4 blocks of one 16-byte vector per thread and step per compute unit: the fastest of the
+    // shapes tried (1-8 vectors per step, 2-32 blocks per compute unit, with and without the
+    // nontemporal hint), at the bandwidth of the runtime's own device-to-device copy
     const size_t want = (n16 + kCopyThreads - 1) / kCopyThreads;
-    const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), (size_t)cus * 8);
+    const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), (size_t)cus * kCopyBlocksPerCu);
     k_hbm_copy<<<grid, kCopyThreads, 0, (hipStream_t)hip_stream>>>((const u32x4*)src, (u32x4*)dst, n16);
     TCL_HIP(hipGetLastError());
     return TC_LCC_OK;
