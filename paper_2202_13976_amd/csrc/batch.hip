@@ -1,21 +1,20 @@
 // Batched path: many graphs counted by one persistent launch.
 //
-// A batch is a list of device-resident graphs.  Its work items are the active
-// vertices of every graph (each graph's own work list, heaviest first), numbered
-// consecutively across the batch.  Waves of a persistent grid take items from a
-// device queue a few at a time, find the item's graph by a binary search over
-// the per-graph item offsets, and count the vertex exactly as the single-graph
-// kernel does (rank bitmap of N+(v) in LDS where it fits, bucket hash otherwise).
-// The count grid is sized to the batch's items (a few grid classes), so a small
-// batch does not start thousands of waves that only find an empty queue.
-// The LCC epilogue runs over chunks of every graph's vertices; it resets each
-// counter to zero after reading it (so the slot's counters are clean for the next
-// batch without a clearing pass), and the block that finishes a graph's last chunk
-// raises that graph's done flag.  Counting and the epilogue form one HIP graph that
-// is captured once per launch shape and replayed for every batch: all sizes and
-// pointers are read from device memory that each submission rewrites, so the
-// capture does not depend on the batch.  Each context holds a few slots (own
-// stream, descriptors, counters and HIP graphs), so batches can overlap on the GPU.
+// A batch is a list of device-resident graphs.  Its work items are the active vertices of
+// every graph (each graph's own work list, heaviest first), numbered consecutively across the
+// batch: first the heavy vertices of all graphs, then the light ones.  A captured HIP graph runs,
+// on one stream, a kernel for the heavy items (a block each), one for the light items (a wave
+// each), the LCC epilogue over chunks of every
+// graph's vertices, and a kernel that raises every graph's done flag.  Workers take items from
+// device queues a few at a time, find an item's graph with a wave-wide search over the
+// per-graph item offsets, and count the vertex as the single-graph kernel does (rank bitmap of
+// N+(v) in LDS where it fits, bucket hash otherwise, HBM search beyond the LDS slice).  The
+// grids are sized to the batch's items (a few grid classes), so a small batch does not start
+// thousands of waves that only find an empty queue.  The epilogue resets each counter to zero
+// after reading it, so the slot's counters are clean for the next batch without a clearing
+// pass.  All sizes and pointers are read from device memory that each submission rewrites, so
+// a capture does not depend on the batch.  Each context holds a few slots (own stream,
+// descriptors, counters and HIP graphs), so batches can overlap on the GPU.
 #include <cstring>
 #include <set>
 
@@ -26,6 +25,8 @@ namespace tcl {
 constexpr int kBatchSlots = 4;
 constexpr int kBatchThreads = 256;
 constexpr int kEpiChunk = 4096;  // vertices per epilogue work item
+constexpr int kQueueStride = 32;  // queue counters 128 bytes apart, one cache line each
+constexpr int kMidGrab = 4;       // mid items per queue access
 
 struct BatchGraph {
     const void* out_off;
@@ -42,8 +43,10 @@ struct BatchGraph {
     double* lcc;
     int64_t n;
     int64_t heavy;      // its heaviest vertices (>= 2^14 probes): vlist[0, heavy), heaviest first
-    int64_t light;      // all its other active vertices: vlist[heavy, heavy + light)
+    int64_t mid;        // its other vertices of the block classes: vlist[heavy, heavy + mid)
+    int64_t light;      // its vertices of the wave class: vlist[heavy + mid, heavy + mid + light)
     int64_t heavy_base; // first heavy item of the graph in the batch
+    int64_t mid_base;   // first mid item of the graph in the batch
     int64_t light_base; // first light item of the graph in the batch
     int64_t chunk_base; // first epilogue chunk of the graph in the batch
     int32_t index;      // position of the graph in the submission (its done flag)
@@ -56,10 +59,15 @@ struct BatchHeader {
     int32_t count;        // graphs in the batch
     int32_t count4;       // graphs [0, count4) use 4-byte offsets, the rest 8-byte ones
     int64_t heavy4, heavy;  // heavy items of the 4-byte graphs, of all graphs
+    int64_t mid4, mid;      // mid items likewise
     int64_t light4, light;  // light items likewise
     uint32_t region;      // LDS bytes per wave
     uint32_t seq;         // submission number, written to the done flags
-    unsigned int queue[4];  // [2 * which]: heavy items, [2 * which + 1]: light grabs taken from the queue
+    unsigned int queue[4];  // [2 * which]: heavy items taken from the queue
+    unsigned int mqueue[2][8 * kQueueStride];  // [which][x * kQueueStride]: mid grabs taken from segment x
+    unsigned int lqueue[2][8 * kQueueStride];  // [which][x * kQueueStride]: light grabs taken from segment x
+    int32_t xcds;         // queue segments of the mid and light items: the GPU's XCDs (at most 8)
+    int32_t pad2_;
     int64_t chunks;       // epilogue chunks of all graphs
     int32_t grab;         // light vertices per queue access when there are plenty
     int32_t pad_;
@@ -84,20 +92,27 @@ __device__ __forceinline__ CountArgs<OffT> batch_args(const BatchGraph& G) {
     return a;
 }
 
-// Last graph g in [g_lo, g_hi) whose items start at or before `item` (HEAVY selects the heavy
-// or the light numbering), found by the whole wave (all lanes active, `item` wave-uniform):
+// Last graph g in [g_lo, g_hi) whose items of `tier` (wave-uniform) start at or before `item`, found by the whole wave (all lanes active, `item` wave-uniform):
 // each round the lanes test 64 evenly spaced graphs of the remaining range at once, so 4096
 // graphs take two rounds of one load each instead of twelve dependent loads.  The bases grow
 // with g and the first graph's base is at most `item`, so the lanes that pass form a prefix.
-template <bool HEAVY>
-__device__ __forceinline__ int batch_graph_of_wave(const BatchGraph* __restrict__ gs, int g_lo, int g_hi,
+constexpr int kTierHeavy = 0, kTierMid = 1, kTierLight = 2;
+
+__device__ __forceinline__ int64_t tier_base(const BatchGraph& G, int tier) {
+    return tier == kTierHeavy ? G.heavy_base : tier == kTierMid ? G.mid_base : G.light_base;
+}
+__device__ __forceinline__ int64_t tier_count(const BatchGraph& G, int tier) {
+    return tier == kTierHeavy ? G.heavy : tier == kTierMid ? G.mid : G.light;
+}
+
+__device__ __forceinline__ int batch_graph_of_wave(const BatchGraph* __restrict__ gs, int g_lo, int g_hi, int tier,
                                                    int64_t item) {
     const int lane = lane_id();
     int lo = g_lo, hi = g_hi;  // the answer lies in [lo, hi)
     while (hi - lo > 1) {
         const int step = (hi - lo + kWave - 1) / kWave;
         const int gi = lo + lane * step;
-        const bool pass = gi < hi && (HEAVY ? gs[gi].heavy_base : gs[gi].light_base) <= item;
+        const bool pass = gi < hi && tier_base(gs[gi], tier) <= item;
         const int k = (int)__popcll(__builtin_amdgcn_ballot_w64(pass));
         lo += (k - 1) * step;
         hi = min(hi, lo + step);
@@ -126,16 +141,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_heavy(const BatchGraph*
     const int64_t hlo = which ? h->heavy4 : 0, hhi = which ? h->heavy : h->heavy4;
     for (int64_t item = hlo + blockIdx.x;;) {
         if (item >= hhi) break;
-        int g = __builtin_amdgcn_readfirstlane(batch_graph_of_wave<true>(gs, g_lo, g_hi, item));
+        int g = __builtin_amdgcn_readfirstlane(batch_graph_of_wave(gs, g_lo, g_hi, kTierHeavy, item));
         while (item >= gs[g].heavy_base + gs[g].heavy) ++g;  // graphs without heavy vertices
         const BatchGraph& G = gs[g];
         const CountArgs<OffT> a = batch_args<OffT>(G);
-        const int32_t v = G.vlist[item - G.heavy_base];
+        const int32_t v = gld(G.vlist, item - G.heavy_base);
         unsigned long long local = 0;
         process_vertex<OffT, TC_LCC_PROBE_AUTO, kBatchThreads / kWave, true>(a, v, lds, rb * (kBatchThreads / kWave),
                                                                               threadIdx.x, w, local, s_tcnt + w * kWave);
         const unsigned long long ws = wave_sum(local);
-        if (lane == 0 && ws) atomicAdd(&G.t[v], ws);
+        if (lane == 0 && ws) gadd(G.t + v, ws);
         if (grid >= hhi - hlo) break;
         if (threadIdx.x == 0) s_item = hlo + grid + (int64_t)atomicAdd(&h->queue[2 * which], 1u);
         __syncthreads();
@@ -145,56 +160,117 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_heavy(const BatchGraph*
 
 }
 
+// One tier of the wave-per-vertex items (mid or light) of offset class `which`: items
+// [lo, hi), taken `grab` at a time.  The items are cut into one contiguous segment per XCD
+// (workgroups are dispatched to the XCDs in turn, so block b runs on XCD b mod nx), each with its
+// own queue counter in its own cache line.  Consecutive items are vertices of the same few
+// graphs, so a graph is mostly counted on one XCD and its lists stay in that XCD's L2 between
+// the in-edges that read them; when a wave's own segment is used up it takes grabs from the
+// other segments' queues in turn.  The first grab of every wave in its own segment is fixed by
+// its index (atomics on one address serialize).  Which wave takes which item changes no count.
 template <typename OffT>
-__global__ __launch_bounds__(kBatchThreads) void k_batch_light(const BatchGraph* __restrict__ gs, BatchHeader* h,
-                                                               int which) {
-    extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t s_tcnt[kBatchThreads];  // per wave: hits of the 64 tails of a chunk
+__device__ __forceinline__ void wave_tier(const BatchGraph* __restrict__ gs, int g_lo, int g_hi, int tier, int64_t lo,
+                                          int64_t hi,
+                                          int grab, int nx, unsigned int* queues, uint8_t* region, uint32_t rb,
+                                          uint32_t* tcnt) {
+    constexpr int kWaves = kBatchThreads / kWave;
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const uint32_t rb = h->region;
-    const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
     const int64_t grid = gridDim.x;
-    uint8_t* region = lds + (size_t)w * rb;
-    const int64_t lo = which ? h->light4 : 0, hi = which ? h->light : h->light4;
-    const int64_t waves = grid * (kBatchThreads / kWave);
-    // light grabs: several items when there are plenty per wave, single ones when few; the
-    // first grab of every wave is fixed by its index
-    const int grab = (hi - lo) >= waves * (int64_t)h->grab * 4 ? h->grab : 1;
-    for (int64_t item = lo + ((grid - 1 - blockIdx.x) * (int64_t)(kBatchThreads / kWave) + w) * grab;;) {
-        if (item >= hi) break;
-        const int64_t end = min(item + (int64_t)grab, hi);
+    auto seg_lo = [&](int x) { return lo + (hi - lo) * x / nx; };
+    // waves whose first grab lies in segment x: those of the blocks b with b mod nx = x
+    auto seg_waves = [&](int x) { return (grid - x + nx - 1) / nx * kWaves; };
+    // the next grab of segment x from its queue, or none when the fixed first grabs cover it
+    auto from_queue = [&](int x) -> int64_t {
+        const int64_t base = seg_lo(x) + seg_waves(x) * grab, end = seg_lo(x + 1);
+        if (base >= end) return INT64_MAX;
+        unsigned int q = 0;
+        if (lane == 0) q = atomicAdd(&queues[x * kQueueStride], 1u);
+        q = __shfl(q, 0, kWave);
+        return base + (int64_t)q * grab;
+    };
+    const int x0 = (int)(blockIdx.x % nx);
+    int xs = x0, visited = 1;
+    int64_t item = seg_lo(x0) + ((int64_t)(blockIdx.x / nx) * kWaves + w) * grab;
+    for (;;) {
+        const int64_t shi = seg_lo(xs + 1);
+        if (item >= shi) {
+            // this segment is used up: the next one's queue
+            if (visited == nx) break;
+            ++visited;
+            xs = xs + 1 == nx ? 0 : xs + 1;
+            item = from_queue(xs);
+            continue;
+        }
+        const int64_t end = min(item + (int64_t)grab, shi);
         // the grab's vertices with their graphs and list bounds, lane q holding item + q, all
         // loaded at once (a grab has at most 64 vertices)
-        int gq = __builtin_amdgcn_readfirstlane(batch_graph_of_wave<false>(gs, g_lo, g_hi, item));
+        int gq = __builtin_amdgcn_readfirstlane(batch_graph_of_wave(gs, g_lo, g_hi, tier, item));
         int32_t hv = 0;
         OffT hb0 = 0, hb1 = 0, hi0 = 0, hi1 = 0;
         if (item + lane < end) {
             const int64_t it = item + lane;
-            while (it >= gs[gq].light_base + gs[gq].light) ++gq;  // graphs without light vertices
+            while (it >= tier_base(gs[gq], tier) + tier_count(gs[gq], tier)) ++gq;  // graphs without such items
             const BatchGraph& GL = gs[gq];
             const OffT* oo = (const OffT*)GL.out_off;
             const OffT* io = (const OffT*)GL.in_off;
-            hv = GL.vlist[GL.heavy + (it - GL.light_base)];
-            hb0 = oo[hv];
-            hb1 = oo[hv + 1];
-            hi0 = io[hv];
-            hi1 = io[hv + 1];
+            const int64_t first = tier == kTierMid ? GL.heavy : GL.heavy + GL.mid;
+            hv = gld(GL.vlist, first + (it - tier_base(GL, tier)));
+            hb0 = gld(oo, hv);
+            hb1 = gld(oo, hv + 1);
+            hi0 = gld(io, hv);
+            hi1 = gld(io, hv + 1);
         }
-        for (int q = 0; item < end; ++item, ++q) {
+        // a software pipeline over the grab: vertex q + 1's first entries of N+(v) and first
+        // in-edges are loaded before vertex q is worked on
+        const int nq = (int)(end - item);
+        auto head = [&](int q) {
+            return VertexHead<OffT>{__builtin_amdgcn_readlane(hv, q), lane_value(hb0, q), lane_value(hb1, q),
+                                    lane_value(hi0, q), lane_value(hi1, q)};
+        };
+        LightPrefetch<OffT> pf = light_prefetch(batch_args<OffT>(gs[__builtin_amdgcn_readlane(gq, 0)]), head(0));
+        for (int q = 0; q < nq; ++q) {
+            LightPrefetch<OffT> next{0, 0, 0, 0};
+            if (q + 1 < nq) next = light_prefetch(batch_args<OffT>(gs[__builtin_amdgcn_readlane(gq, q + 1)]), head(q + 1));
             const BatchGraph& G = gs[__builtin_amdgcn_readlane(gq, q)];
-            const CountArgs<OffT> a = batch_args<OffT>(G);
-            const VertexHead<OffT> hd{__builtin_amdgcn_readlane(hv, q), lane_value(hb0, q), lane_value(hb1, q),
-                                      lane_value(hi0, q), lane_value(hi1, q)};
+            const VertexHead<OffT> hd = head(q);
             unsigned long long local = 0;
-            process_vertex<OffT, TC_LCC_PROBE_AUTO, 1, true>(a, hd, region, rb, lane, 0, local, s_tcnt + w * kWave);
+            process_light<OffT>(batch_args<OffT>(G), hd, pf, region, rb, local, tcnt);
             const unsigned long long ws = wave_sum(local);
-            if (lane == 0 && ws) atomicAdd(&G.t[hd.v], ws);
+            if (lane == 0 && ws) gadd(G.t + hd.v, ws);
+            pf = next;
         }
-        if (waves * grab >= hi - lo) break;
-        unsigned int q = 0;
-        if (lane == 0) q = atomicAdd(&h->queue[2 * which + 1], 1u);
-        q = __shfl(q, 0, kWave);
-        item = lo + (waves + (int64_t)q) * grab;
+        item = from_queue(xs);
+    }
+}
+
+// All vertices below the heavy threshold, one wave each in its slice of the LDS: first the mid
+// items of every graph (the rest of the block classes: more probes than a wave-class vertex),
+// a few per queue access, then the light items (the wave class), several per access when there
+// are plenty.  Taking the larger items first keeps a grab of large items from ending the kernel
+// late; grabs of 64 light items took 13.9 ms instead of 8.5 for the 4096-graph batch.
+template <typename OffT>
+__global__ __launch_bounds__(kBatchThreads, 6) void k_batch_light(const BatchGraph* __restrict__ gs, BatchHeader* h,
+                                                               int which) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t s_tcnt[kBatchThreads];  // per wave: hits of the 64 tails of a chunk
+    const int w = threadIdx.x / kWave;
+    const uint32_t rb = h->region;
+    const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
+    const int64_t grid = gridDim.x;
+    const int64_t waves = grid * (kBatchThreads / kWave);
+    uint8_t* region = lds + (size_t)w * rb;
+    uint32_t* tcnt = s_tcnt + w * kWave;
+    const int nx = (int)min<int64_t>(max(h->xcds, 1), min<int64_t>(grid, 8));
+    // one copy of the code for both tiers (the loop is not unrolled)
+#pragma unroll 1
+    for (int tier = kTierMid; tier <= kTierLight; ++tier) {
+        const bool m = tier == kTierMid;
+        const int64_t lo = m ? (which ? h->mid4 : 0) : (which ? h->light4 : 0);
+        const int64_t hi = m ? (which ? h->mid : h->mid4) : (which ? h->light : h->light4);
+        // light grabs: several items when there are plenty per wave, single ones when few
+        const int grab = m ? kMidGrab : ((hi - lo) >= waves * (int64_t)h->grab * 4 ? h->grab : 1);
+        wave_tier<OffT>(gs, g_lo, g_hi, tier, lo, hi, grab, nx, m ? h->mqueue[which] : h->lqueue[which], region, rb,
+                        tcnt);
     }
 }
 
@@ -294,6 +370,7 @@ struct Engine {
     uint32_t next_seq = 1;
     std::mutex mu;
     std::map<uint64_t, int> completed;  // tickets finished before their poll: graphs done
+    int32_t xcds = 1;                   // the device's XCDs (light segments of the batched launch)
 };
 
 // created with the context (tc_lcc_ctx_create), so no two threads race to create it
@@ -472,11 +549,18 @@ void finish_slot(Slot& s) {
 }  // namespace
 
 tc_lcc_status batch_engine_create(tc_lcc_ctx ctx) {
-    ctx->batch = new (std::nothrow) Engine();
-    if (!ctx->batch) {
+    Engine* e = new (std::nothrow) Engine();
+    if (!e) {
         set_error("batch: engine allocation failed");
         return TC_LCC_OUT_OF_MEMORY;
     }
+    int xcc = 1;
+    if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, ctx->pool->device()) != hipSuccess) {
+        (void)hipGetLastError();
+        xcc = 1;
+    }
+    e->xcds = std::min(std::max(xcc, 1), 8);
+    ctx->batch = e;
     return TC_LCC_OK;
 }
 
@@ -524,7 +608,7 @@ namespace {
 // after a tuning change may rebuild the schedule; it first waits for the batches that hold
 // the graph, and it cannot start while a submission holds the engine's lock).
 struct Plan {
-    int64_t heavy = 0, light = 0;
+    int64_t heavy = 0, mid = 0, light = 0;
     bool solo = false;
 };
 
@@ -622,7 +706,8 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
         int64_t big = 0;
         for (int c = 0; c <= 40 - heavy_bits && c < 48; ++c) big += d.class_count[c];
         p.heavy = big;
-        p.light = d.n_block - big + d.n_wave;
+        p.mid = d.n_block - big;
+        p.light = d.n_wave;
         need = std::max(need, std::min(r, kRegionClasses[kNumRegionClasses - 1]));
         need_scratch += (size_t)d.n;
         (d.off_bytes == 4 ? ord4 : ord8).push_back(i);
@@ -660,7 +745,7 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
         return why;
     };
 
-    int64_t heavy = 0, light = 0, heavy4 = 0, light4 = 0, chunk = 0;
+    int64_t heavy = 0, mid = 0, light = 0, heavy4 = 0, mid4 = 0, light4 = 0, chunk = 0;
     size_t soff = 0;
     int k = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -682,8 +767,10 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
             b.lcc = lcc ? lcc[i] : nullptr;
             b.n = d.n;
             b.heavy = p.heavy;
+            b.mid = p.mid;
             b.light = p.light;
             b.heavy_base = heavy;
+            b.mid_base = mid;
             b.light_base = light;
             b.chunk_base = chunk;
             b.index = i;
@@ -691,12 +778,14 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
             b.pad_chunks = 0;
             b.pad_ = 0;
             heavy += b.heavy;
+            mid += b.mid;
             light += b.light;
             chunk += b.nchunks;
             soff += (size_t)d.n;
         }
         if (pass == 0) {
             heavy4 = heavy;
+            mid4 = mid;
             light4 = light;
         }
     }
@@ -704,18 +793,26 @@ tc_lcc_status tcl::batch_submit_with(tc_lcc_ctx ctx, int count, const tc_lcc_gra
     s->h_hdr->count4 = (int32_t)ord4.size();
     s->h_hdr->heavy4 = heavy4;
     s->h_hdr->heavy = heavy;
+    s->h_hdr->mid4 = mid4;
+    s->h_hdr->mid = mid;
     s->h_hdr->light4 = light4;
     s->h_hdr->light = light;
     s->h_hdr->region = region;
     s->h_hdr->seq = seq;
     for (unsigned int& q : s->h_hdr->queue) q = 0;
+    for (auto& row : s->h_hdr->mqueue)
+        for (unsigned int& q : row) q = 0;
+    for (auto& row : s->h_hdr->lqueue)
+        for (unsigned int& q : row) q = 0;
+    s->h_hdr->xcds = e->xcds;
+    s->h_hdr->pad2_ = 0;
     s->h_hdr->chunks = chunk;
     s->h_hdr->grab = grab;
     s->h_hdr->pad_ = 0;
 
     if (nb > 0) {
         hipGraphExec_t exec = nullptr;
-        st = capture(*s, region, !ord4.empty(), !ord8.empty(), grid_class(heavy, light), ctx->cu_count, &exec);
+        st = capture(*s, region, !ord4.empty(), !ord8.empty(), grid_class(heavy, mid + light), ctx->cu_count, &exec);
         if (st != TC_LCC_OK) return fail(st);
         if (hipMemcpyAsync(s->d_graphs, s->h_graphs, (size_t)nb * sizeof(BatchGraph), hipMemcpyHostToDevice,
                            s->stream) != hipSuccess ||

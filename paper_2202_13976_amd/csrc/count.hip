@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_global(CountArgs<OffT> 
         const int32_t v = a.vlist[a.n_block + a.n_wave + it];
         const OffT b0 = a.out_off[v];
         Table tb;
-        tb.keys = const_cast<int32_t*>(a.adj + b0);
+        tb.gkeys = a.adj + b0;
         tb.T = (int32_t)(a.out_off[v + 1] - b0);
         tb.tg = a.t;
         unsigned long long local = 0;

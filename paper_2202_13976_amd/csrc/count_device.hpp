@@ -9,6 +9,21 @@ namespace tcl {
 
 constexpr int kUnroll = 4;  // prefetched windows of 64 candidates
 
+// Global-memory accessors.  A pointer that a kernel reads from memory (the batched path's graph
+// descriptors) is a generic address to the compiler, and generic (flat) loads and atomics count
+// against the same wait counter as LDS operations, so every LDS synchronisation of a walk would
+// also wait for the memory operations in flight.  Every array the count reads or adds to lies in
+// global memory; accessing it through a pointer of the global address space says so (pointers
+// from kernel arguments are known to be global already).
+template <typename T, typename I>
+__device__ __forceinline__ T gld(const T* p, I i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+__device__ __forceinline__ void gadd(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename OffT>
 struct CountArgs {
     const OffT* out_off;
@@ -83,6 +98,17 @@ __device__ __forceinline__ int sorted_find(const int32_t* keys, int32_t T, int32
     return (lo < T && keys[lo] == x) ? lo : -1;
 }
 
+// The same search in a list that lies in global memory: is x in it?
+__device__ __forceinline__ bool sorted_find_global(const int32_t* keys, int32_t T, int32_t x) {
+    int lo = 0, hi = T;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (gld(keys, mid) < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < T && gld(keys, lo) == x;
+}
+
 // A window: 64 consecutive candidates of one tail (lane i takes candidate base + i).
 template <typename OffT>
 struct Win {
@@ -104,7 +130,8 @@ struct Win {
 constexpr int kProbeGlobal = 16;
 
 struct Table {
-    int32_t* keys;
+    int32_t* keys;           // LDS: hash slots or the sorted list
+    const int32_t* gkeys;    // global mode: N+(v) where it lies in HBM
     uint32_t* cnt;
     unsigned long long* tg;  // global mode: t
     uint32_t* bm;
@@ -153,8 +180,8 @@ __device__ __forceinline__ bool probe_one(const Table& tb, int32_t x, bool val) 
             b = pending ? ((b + 1) & tb.nb_mask) : b;
         }
     } else if constexpr (MODE == kProbeGlobal) {
-        hit = val && sorted_find(tb.keys, tb.T, x) >= 0;
-        if (hit) atomicAdd(&tb.tg[x], 1ull);
+        hit = val && sorted_find_global(tb.gkeys, tb.T, x);
+        if (hit) gadd(tb.tg + x, 1ull);
     } else {
         const int sl = sorted_find(tb.keys, tb.T, x);
         hit = val && sl >= 0;
@@ -178,14 +205,14 @@ struct InEdges {
 // hold u and the position p of v in N+(u); the tail is N+(u) after p.
 template <typename OffT>
 __device__ __forceinline__ void load_in_edge(const CountArgs<OffT>& a, OffT k, int32_t& u, OffT& st, int32_t& len) {
-    u = a.in_u[k];
+    u = gld(a.in_u, k);
     if constexpr (kCompactOff<OffT>) {
-        const OffT o0 = a.out_off[u], o1 = a.out_off[u + 1];
-        st = o0 + (OffT)a.in_pos[k] + 1;
+        const OffT o0 = gld(a.out_off, u), o1 = gld(a.out_off, u + 1);
+        st = o0 + (OffT)gld(a.in_pos, k) + 1;
         len = (int32_t)(o1 - st);
     } else {
-        st = a.in_start[k];
-        len = a.in_len[k];
+        st = gld(a.in_start, k);
+        len = gld(a.in_len, k);
     }
 }
 
@@ -204,7 +231,7 @@ __device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a
 
 template <int NWAVES, typename OffT>
 __device__ __forceinline__ InEdges<OffT> first_in_edges(const CountArgs<OffT>& a, int32_t v, int wig) {
-    return first_in_edges<NWAVES>(a, a.in_off[v], a.in_off[v + 1], wig);
+    return first_in_edges<NWAVES>(a, gld(a.in_off, v), gld(a.in_off, v + 1), wig);
 }
 
 // The waves of a group walk the tails of v's in-edges, 64 in-edges (a chunk) at a time,
@@ -290,7 +317,7 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
             j = gjv;
             lim = gend4 - gbase4;
             const uint32_t off4 = min((uint32_t)gbase4 + lane4, glast4);
-            const int32_t x = *(const int32_t*)(tptr + off4);
+            const int32_t x = gld((const int32_t*)(tptr + off4), 0);
             advance();
             return x;
         };
@@ -364,7 +391,7 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         }
         asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(__builtin_amdgcn_readfirstlane(cur_c)), "{m0}"(cur_j));
         local += mine;
-        if (ok && mine) atomicAdd(&a.t[u], (unsigned long long)mine);
+        if (ok && mine) gadd(a.t + u, (unsigned long long)mine);
     }
 }
 
@@ -387,7 +414,7 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
     const int32_t lb = tb.T;
     const int32_t* B = tb.keys;
     const float scale = (float)a.merge_x100 * 0.01f;
-    const OffT i0 = a.in_off[v], i1 = a.in_off[v + 1];
+    const OffT i0 = gld(a.in_off, v), i1 = gld(a.in_off, v + 1);
     for (OffT cb = i0; cb < i1; cb += (OffT)kWave) {
         const OffT k = cb + lane;
         int32_t u = 0;
@@ -459,7 +486,7 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
                 }
             }
             const uint32_t ct = wave_sum(c);
-            if (lane == 0 && ct) atomicAdd(&a.t[tu], (unsigned long long)ct);
+            if (lane == 0 && ct) gadd(a.t + tu, (unsigned long long)ct);
             local += c;
         }
     }
@@ -531,7 +558,7 @@ __device__ __forceinline__ void walk_flat(const CountArgs<OffT>& a, const InEdge
                     } else {
                         d = (OffT)__shfl((int32_t)dk, k, kWave);
                     }
-                    if (vs[r]) xs[r] = a.adj[d + (OffT)c];
+                    if (vs[r]) xs[r] = gld(a.adj, d + (OffT)c);
                 }
             }
 #pragma unroll
@@ -566,7 +593,7 @@ __device__ __forceinline__ void walk_flat(const CountArgs<OffT>& a, const InEdge
         }
         wave_lds_sync();
         const uint32_t mine = tcnt[lane];
-        if (mine) atomicAdd(&a.t[u], (unsigned long long)mine);
+        if (mine) gadd(a.t + u, (unsigned long long)mine);
         wave_lds_sync();
     }
 }
@@ -590,7 +617,7 @@ struct VertexHead {
 
 template <typename OffT>
 __device__ __forceinline__ VertexHead<OffT> vertex_head(const CountArgs<OffT>& a, int32_t v) {
-    return VertexHead<OffT>{v, a.out_off[v], a.out_off[v + 1], a.in_off[v], a.in_off[v + 1]};
+    return VertexHead<OffT>{v, gld(a.out_off, v), gld(a.out_off, v + 1), gld(a.in_off, v), gld(a.in_off, v + 1)};
 }
 
 // FALLBACK (the batched kernels): a vertex whose bucket hash does not fit the region either is
@@ -615,14 +642,14 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const V
     if constexpr (PROBE == TC_LCC_PROBE_SORTED || PROBE == TC_LCC_PROBE_MERGE) {
         mode = PROBE;
     } else {
-        tb.span = (uint32_t)(nv[dv - 1] - v);
+        tb.span = (uint32_t)(gld(nv, dv - 1) - v);
         tb.words = (tb.span + 31u) >> 5;
         mode = (PROBE != TC_LCC_PROBE_HASH && bitmap_bytes(tb.words, dv) <= region_bytes) ? TC_LCC_PROBE_BITMAP
                                                                                            : TC_LCC_PROBE_HASH;
         if constexpr (FALLBACK) {
             if (mode == TC_LCC_PROBE_HASH && 8u * (uint32_t)hash_table_slots(dv) > region_bytes) {
                 mode = kProbeGlobal;
-                tb.keys = const_cast<int32_t*>(nv);
+                tb.gkeys = nv;
                 tb.T = dv;
                 tb.tg = a.t;
             }
@@ -646,9 +673,9 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const V
         for (int j = gtid; j < dv; j += gsize) tb.cnt[j] = 0u;
         group_sync<NWAVES>();
         for (int j = gtid; j < dv; j += gsize) {
-            const uint32_t i = (uint32_t)(nv[j] - tb.base);
+            const uint32_t i = (uint32_t)(gld(nv, j) - tb.base);
             atomicOr(&tb.bm[2 * (i >> 5)], 1u << (i & 31u));
-            if (j == 0 || ((uint32_t)(nv[j - 1] - tb.base) >> 5) != (i >> 5)) tb.bm[2 * (i >> 5) + 1] = (uint32_t)j;
+            if (j == 0 || ((uint32_t)(gld(nv, j - 1) - tb.base) >> 5) != (i >> 5)) tb.bm[2 * (i >> 5) + 1] = (uint32_t)j;
         }
     } else if (mode == TC_LCC_PROBE_HASH) {
         const int32_t T = hash_table_slots(dv);
@@ -663,13 +690,13 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const V
             tb.cnt[s] = 0;
         }
         group_sync<NWAVES>();
-        for (int j = gtid; j < dv; j += gsize) hash_insert(tb.keys, tb.nb_mask, tb.logNB, nv[j]);
+        for (int j = gtid; j < dv; j += gsize) hash_insert(tb.keys, tb.nb_mask, tb.logNB, gld(nv, j));
     } else {
         tb.T = dv;
         tb.keys = (int32_t*)region;
         tb.cnt = (uint32_t*)(tb.keys + dv);
         for (int j = gtid; j < dv; j += gsize) {
-            tb.keys[j] = nv[j];
+            tb.keys[j] = gld(nv, j);
             tb.cnt[j] = 0;
         }
     }
@@ -694,12 +721,12 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, const V
             // test keeps the flush in bounds without resting on that
             const uint32_t c = tb.cnt[s];
             const int32_t key = tb.keys[s];
-            if (c && key >= 0) atomicAdd(&a.t[key], (unsigned long long)c);
+            if (c && key >= 0) gadd(a.t + key, (unsigned long long)c);
         }
     } else {
         for (int j = gtid; j < dv; j += gsize) {
             const uint32_t c = tb.cnt[j];
-            if (c) atomicAdd(&a.t[nv[j]], (unsigned long long)c);
+            if (c) gadd(a.t + gld(nv, j), (unsigned long long)c);
         }
     }
     group_sync<NWAVES>();
@@ -710,6 +737,117 @@ __device__ __forceinline__ void process_vertex(const CountArgs<OffT>& a, int32_t
                                                uint32_t region_bytes, int gtid, int wig, unsigned long long& local,
                                                uint32_t* tcnt = nullptr) {
     process_vertex<OffT, PROBE, NWAVES, FALLBACK>(a, vertex_head(a, v), region, region_bytes, gtid, wig, local, tcnt);
+}
+
+// What a light vertex of the batched launch needs first, loaded while the previous vertex is
+// worked on: this lane's entry of N+(v) (entry `lane`, for the first 64) and this lane's in-edge
+// of v's first chunk (u, tail start, tail length).
+template <typename OffT>
+struct LightPrefetch {
+    int32_t x;
+    int32_t u;
+    OffT st;
+    int32_t len;
+};
+
+template <typename OffT>
+__device__ __forceinline__ LightPrefetch<OffT> light_prefetch(const CountArgs<OffT>& a, const VertexHead<OffT>& hd) {
+    LightPrefetch<OffT> p{0, 0, 0, 0};
+    const int lane = lane_id();
+    if ((OffT)lane < hd.b1 - hd.b0) p.x = gld(a.adj, hd.b0 + (OffT)lane);
+    const OffT k = hd.i0 + (OffT)lane;
+    if (k < hd.i1) load_in_edge(a, k, p.u, p.st, p.len);
+    return p;
+}
+
+// A light vertex of the batched launch, one wave, as process_vertex with NWAVES = 1 and
+// FALLBACK, but with its first loads already done (pf): N+(v) is staged from registers (the
+// previous entry of each lane's from its neighbour lane), its last entry read from the lane that
+// holds it, and the flush adds to t(w) by the entry each lane still holds, so the vertex waits on
+// global memory only for its candidates (and for entries beyond the first 64).
+template <typename OffT>
+__device__ __forceinline__ void process_light(const CountArgs<OffT>& a, const VertexHead<OffT>& hd,
+                                              const LightPrefetch<OffT>& pf, uint8_t* region, uint32_t region_bytes,
+                                              unsigned long long& local, uint32_t* tcnt) {
+    const int lane = lane_id();
+    const int32_t v = hd.v;
+    const int32_t dv = (int32_t)(hd.b1 - hd.b0);
+    const int32_t* nv = a.adj + hd.b0;
+    const InEdges<OffT> ie{hd.i0, hd.i1, pf.u, pf.st, pf.len};
+    // entry j of N+(v) (j wave-uniform below 64: the lane that holds it)
+    const int32_t last = dv <= kWave ? __builtin_amdgcn_readlane(pf.x, dv - 1) : gld(nv, dv - 1);
+
+    Table tb;
+    tb.base = v + 1;
+    tb.span = (uint32_t)(last - v);
+    tb.words = (tb.span + 31u) >> 5;
+    int mode = bitmap_bytes(tb.words, dv) <= region_bytes ? TC_LCC_PROBE_BITMAP : TC_LCC_PROBE_HASH;
+    if (mode == TC_LCC_PROBE_HASH && 8u * (uint32_t)hash_table_slots(dv) > region_bytes) {
+        tb.gkeys = nv;
+        tb.T = dv;
+        tb.tg = a.t;
+        walk_flat<OffT, kProbeGlobal, 1>(a, ie, tb, tcnt, 0, local);
+        wave_lds_sync();
+        return;
+    }
+
+    // ---- stage N+(v): lane l holds entry j0 + l of each round of 64
+    if (mode == TC_LCC_PROBE_BITMAP) {
+        tb.bm = (uint32_t*)region;
+        tb.cnt = (uint32_t*)(region + 8u * (tb.words + 1u));  // dv counters, then 64 spare words
+        tb.T = dv;
+        for (uint32_t s = lane; s <= tb.words; s += kWave) tb.bm[2 * s] = 0u;  // with the guard word
+        for (int j = lane; j < dv; j += kWave) tb.cnt[j] = 0u;
+        wave_lds_sync();
+        int32_t carry = 0;  // entry j0 - 1
+        for (int j0 = 0; j0 < dv; j0 += kWave) {
+            const int j = j0 + lane;
+            const int32_t x = j0 == 0 ? pf.x : (j < dv ? gld(nv, j) : 0);
+            int32_t xp = __shfl_up(x, 1, kWave);
+            if (lane == 0) xp = carry;
+            carry = __builtin_amdgcn_readlane(x, kWave - 1);
+            if (j < dv) {
+                const uint32_t i = (uint32_t)(x - tb.base);
+                atomicOr(&tb.bm[2 * (i >> 5)], 1u << (i & 31u));
+                if (j == 0 || ((uint32_t)(xp - tb.base) >> 5) != (i >> 5)) tb.bm[2 * (i >> 5) + 1] = (uint32_t)j;
+            }
+        }
+    } else {
+        const int32_t T = hash_table_slots(dv);
+        const uint32_t nb = (uint32_t)T >> 2;
+        tb.T = T;
+        tb.nb_mask = nb - 1;
+        tb.logNB = 31 - __clz(nb);
+        tb.keys = (int32_t*)region;
+        tb.cnt = (uint32_t*)(tb.keys + T);
+        for (int s = lane; s < T; s += kWave) {
+            tb.keys[s] = -1;
+            tb.cnt[s] = 0;
+        }
+        wave_lds_sync();
+        for (int j = lane; j < dv; j += kWave) hash_insert(tb.keys, tb.nb_mask, tb.logNB, j < kWave ? pf.x : gld(nv, j));
+    }
+    wave_lds_sync();
+
+    // ---- probe the tails of the in-edges
+    if (mode == TC_LCC_PROBE_BITMAP) walk_flat<OffT, TC_LCC_PROBE_BITMAP, 1>(a, ie, tb, tcnt, 0, local);
+    else walk_flat<OffT, TC_LCC_PROBE_HASH, 1>(a, ie, tb, tcnt, 0, local);
+    wave_lds_sync();
+
+    // ---- flush the per-entry counters of N+(v)
+    if (mode == TC_LCC_PROBE_HASH) {
+        for (int s = lane; s < tb.T; s += kWave) {
+            const uint32_t c = tb.cnt[s];
+            const int32_t key = tb.keys[s];
+            if (c && key >= 0) gadd(a.t + key, (unsigned long long)c);
+        }
+    } else {
+        for (int j = lane; j < dv; j += kWave) {
+            const uint32_t c = tb.cnt[j];
+            if (c) gadd(a.t + (j < kWave ? pf.x : gld(nv, j)), (unsigned long long)c);
+        }
+    }
+    wave_lds_sync();
 }
 
 }  // namespace tcl
