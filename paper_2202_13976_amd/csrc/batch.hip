@@ -18,7 +18,7 @@
 #include <cstring>
 #include <set>
 
-#include "count_device.hpp"
+#include "batch_device.hpp"
 
 namespace tcl {
 
@@ -131,7 +131,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_heavy(const BatchGraph*
                                                                int which) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ int64_t s_item;
-    __shared__ uint32_t s_tcnt[kBatchThreads];  // per wave: hits of the 64 tails of a chunk
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint32_t rb = h->region;
     const int g_lo = which ? h->count4 : 0, g_hi = which ? h->count : h->count4;
@@ -148,7 +147,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_heavy(const BatchGraph*
         const int32_t v = gld(G.vlist, item - G.heavy_base);
         unsigned long long local = 0;
         process_vertex<OffT, TC_LCC_PROBE_AUTO, kBatchThreads / kWave, true>(a, v, lds, rb * (kBatchThreads / kWave),
-                                                                              threadIdx.x, w, local, s_tcnt + w * kWave);
+                                                                              threadIdx.x, w, local);
         const unsigned long long ws = wave_sum(local);
         if (lane == 0 && ws) gadd(G.t + v, ws);
         if (grid >= hhi - hlo) break;
