@@ -246,10 +246,13 @@ __device__ __forceinline__ void wave_tier(const BatchGraph* __restrict__ gs, int
 // items of every graph (the rest of the block classes: more probes than a wave-class vertex),
 // a few per queue access, then the light items (the wave class), several per access when there
 // are plenty.  Taking the larger items first keeps a grab of large items from ending the kernel
-// late; grabs of 64 light items took 13.9 ms instead of 8.5 for the 4096-graph batch.
+// late; grabs of 64 light items took 13.9 ms instead of 8.5 for the 4096-graph batch.  The
+// kernel is bound by the latency of each vertex's few dependent steps, so resident waves matter
+// more than registers: seven waves per SIMD (72 VGPRs, a few spilled) beat six (6.8 against 7.1
+// ms for that batch) and four (8.3 ms).
 template <typename OffT>
-__global__ __launch_bounds__(kBatchThreads, 6) void k_batch_light(const BatchGraph* __restrict__ gs, BatchHeader* h,
-                                                               int which) {
+__global__ __launch_bounds__(kBatchThreads, 7) void k_batch_light(const BatchGraph* __restrict__ gs, BatchHeader* h,
+                                                                  int which) {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_tcnt[kBatchThreads];  // per wave: hits of the 64 tails of a chunk
     const int w = threadIdx.x / kWave;
@@ -266,8 +269,10 @@ __global__ __launch_bounds__(kBatchThreads, 6) void k_batch_light(const BatchGra
         const bool m = tier == kTierMid;
         const int64_t lo = m ? (which ? h->mid4 : 0) : (which ? h->light4 : 0);
         const int64_t hi = m ? (which ? h->mid : h->mid4) : (which ? h->light : h->light4);
-        // light grabs: several items when there are plenty per wave, single ones when few
-        const int grab = m ? kMidGrab : ((hi - lo) >= waves * (int64_t)h->grab * 4 ? h->grab : 1);
+        // several items per grab when there are plenty per wave (light: four grabs per wave; mid:
+        // one), single ones when few (a small batch's latency is its longest wave)
+        const int want = m ? kMidGrab : h->grab;
+        const int grab = (hi - lo) >= waves * (int64_t)want * (m ? 1 : 4) ? want : 1;
         wave_tier<OffT>(gs, g_lo, g_hi, tier, lo, hi, grab, nx, m ? h->mqueue[which] : h->lqueue[which], region, rb,
                         tcnt);
     }

@@ -19,7 +19,7 @@ namespace tcl {
 // at once); the hits of one tail in one window are summed by a popcount over that tail's lanes
 // and added to the tail's LDS counter (tcnt: 64 words of this wave) by its last lane; the
 // tails' counts go to t(u) once the chunk is done.
-constexpr int kFlatRound = 4;
+constexpr int kFlatRound = 3;
 
 template <typename OffT, int MODE, int NWAVES = 1>
 __device__ __forceinline__ void walk_flat(const CountArgs<OffT>& a, const InEdges<OffT>& ie, const Table& tb,
