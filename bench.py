@@ -346,6 +346,109 @@ def streamed_bench(ctx, torch, pkg, log_fn, scale: int, ef: int = 16, seed: int 
                        "lcc_equals_host_division": lcc_ok}}
 
 
+def large_bench(torch, pkg, log_fn, scale: int, ef: int = 16, seed: int = 1, sample: int = 24, reps: int = 3):
+    """R-MAT at 2^scale vertices and ef * 2^scale raw pairs (Table II's recipe, the host
+    generator), built by tc_lcc_build_csr from the raw pairs in HBM (the one-pass build; offsets
+    of 4 bytes while the pairs number fewer than 2^31) and counted.  Reports the build and count
+    times and the count kernel's roofline, checks every vertex against invariants (sum t = 0 mod 3,
+    t <= C(d, 2), LCC equal to 2 t / (d (d - 1)) divided on the host in binary64), and checks t and
+    LCC of `sample` vertices (drawn uniformly among those with at least two pair ends, plus the one
+    with the most) against the oracle's count straight from the raw pairs (on the host, a few
+    seconds per vertex at scale 26)."""
+    import numpy as np
+    import oracle
+    import synth
+    n, m_in = 1 << scale, ef << scale
+    log_fn(f"[bench] large leg: generating R-MAT S{scale} EF{ef} ({m_in} pairs) on the host")
+    t0 = time.perf_counter()
+    n, s, d = synth.rmat_scale(scale, ef, seed)
+    gen_s = time.perf_counter() - t0
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(s).to(dev)
+    dst = torch.from_numpy(d).to(dev)
+    ctx = pkg.Context(0)
+    ctx.set_profiling(True)
+    try:
+        build_ms, count_ms, walls = [], [], []
+        g = None
+        for r in range(reps):
+            log_fn(f"[bench] large leg: build {r + 1} of {reps}")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g = ctx.build_csr(n, src, dst, offset_bytes=0)
+            torch.cuda.synchronize()
+            walls.append((time.perf_counter() - t1) * 1e3)
+            tm = g.timings().as_dict()
+            build_ms.append(sum(v for k, v in tm.items() if k.startswith("build")))
+            if r + 1 < reps:
+                g.free()
+        del src, dst
+        torch.cuda.empty_cache()
+        info = g.info()
+        tri = torch.empty(n, dtype=torch.int64, device=dev)
+        lcc = torch.empty(n, dtype=torch.float64, device=dev)
+        for r in range(reps + 1):
+            log_fn(f"[bench] large leg: count {r + 1} of {reps + 1}")
+            g.run(tri, lcc)
+            torch.cuda.synchronize()
+            if r:
+                count_ms.append(g.timings().run_count_ms)
+        deg = np.empty(n, dtype=np.int64)
+        pkg.lib().tc_lcc_graph_export(g.handle, deg.ctypes.data, None, None, None)
+        g.free()
+        t = tri.cpu().numpy().view(np.uint64)
+        lv = lcc.cpu().numpy()
+        del tri, lcc
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+    total = int(t.sum(dtype=np.uint64))
+    du = deg.astype(np.uint64)
+    big = deg >= 2
+    bound_ok = bool(np.all(t[big] <= du[big] * (du[big] - np.uint64(1)) // np.uint64(2))) and bool(np.all(t[~big] == 0))
+    want = np.zeros(n, dtype=np.float64)
+    want[big] = (2 * t[big]).astype(np.float64) / (du[big] * (du[big] - np.uint64(1))).astype(np.float64)
+    lcc_ok = want.tobytes() == lv.tobytes()
+    res = {"workload": f"rmat_s{scale}_ef{ef} (R-MAT {RMAT_ABC_TXT}, host generator, seed {seed})",
+           "n": n, "raw_pairs": m_in, "m_undirected": int(info.m), "offset_bytes": int(info.offset_bytes),
+           "entry": "tc_lcc_build_csr + tc_lcc_run", "generation_s": gen_s,
+           "build_ms": float(np.median(build_ms)), "build_wall_ms": float(np.median(walls)),
+           "count_ms": float(np.median(count_ms)),
+           "teps_build_and_count": int(info.m) / ((np.median(build_ms) + np.median(count_ms)) * 1e-3),
+           "graph": {"wedges": int(info.wedges), "kept_in_edges": int(info.kept_in_edges),
+                     "max_out_degree": int(info.max_out_degree), "max_degree": int(info.max_degree),
+                     "device_bytes": int(info.device_bytes), "triangles": total // 3},
+           "checks": {"sum_t_divisible_by_3": total % 3 == 0, "t_at_most_pairs_of_neighbours": bound_ok,
+                      "lcc_equals_host_division": lcc_ok}}
+    alg = count_bytes(info)
+    c = res["count_ms"] * 1e-3
+    res["roofline"] = {"bound": "hbm", "alg_bytes_per_launch": alg, "achieved": alg / c / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": alg / c / 1e9 / HBM_PEAK_GBS}
+    if sample > 0:
+        # vertices with at least two pair ends (counted on the host), uniformly, and the vertex with
+        # the most pair ends
+        ends = np.bincount(s, minlength=n) + np.bincount(d, minlength=n)
+        rng = np.random.default_rng(seed)
+        vs = np.sort(rng.choice(np.flatnonzero(ends >= 2), size=sample - 1, replace=False))
+        vs = np.append(vs, int(np.argmax(ends)))
+        del ends
+        t2 = time.perf_counter()
+        tr, dr = [], []
+        for i, v in enumerate(vs):
+            a, b = oracle.tc_vertex_pairs(n, s, d, int(v))
+            tr.append(a)
+            dr.append(b)
+            log_fn(f"[bench] large leg: oracle vertex {i + 1} of {sample}: v={int(v)} d={b} t={a}")
+        tr = np.array(tr, dtype=np.uint64)
+        lr = np.array([oracle.lcc_one(int(a), int(b)) for a, b in zip(tr, dr)])
+        res["oracle_sample"] = {"vertices": int(sample), "seconds": time.perf_counter() - t2,
+                                "degrees_equal": bool(np.array_equal(np.array(dr), deg[vs])),
+                                "t_equal": bool(np.array_equal(tr, t[vs])),
+                                "lcc_bits_equal": lr.tobytes() == lv[vs].tobytes(),
+                                "sampled_triangles": int(tr.sum())}
+    return res
+
+
 def batch_bench(ctx, torch, pkg, log_fn, reps: int = 3, autotune: bool = True):
     """4096 uneven graphs: a loop of single-graph runs against one batched submission."""
     import numpy as np
@@ -612,6 +715,10 @@ def main():
                          "0 skips it.  Scales above 16 are refused: a run at scale 26 ended in a GPU "
                          "memory fault whose cause is not found yet")
     ap.add_argument("--streamed-only", action="store_true", help="run only the streamed leg")
+    ap.add_argument("--large-scale", type=int, default=0,
+                    help="run only a large leg: R-MAT at this scale from the host generator through the "
+                         "one-pass build (pairs in HBM), with sampled oracle checks; 0 skips it")
+    ap.add_argument("--large-sample", type=int, default=24, help="vertices the large leg checks against the oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB with the library's streaming copy kernel 3 times "
                          "(reference for HBM counters)")
@@ -628,6 +735,11 @@ def main():
     import numpy as np
     import torch
     import paper_2202_13976_amd as pkg
+
+    if args.large_scale:
+        res = large_bench(torch, pkg, log, args.large_scale, sample=args.large_sample)
+        print(json.dumps({"large": res}), flush=True)
+        return
 
     if args.streamed_only:
         ctx = pkg.Context(0)

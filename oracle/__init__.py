@@ -56,6 +56,8 @@ def _load():
         lib.oracle_tc_brute.restype = None
         lib.oracle_tc_vertex.argtypes = [vp, vp, i32, vp]
         lib.oracle_tc_vertex.restype = u64
+        lib.oracle_tc_vertex_pairs.argtypes = [i64, vp, vp, i32, vp, vp]
+        lib.oracle_tc_vertex_pairs.restype = u64
         lib.oracle_lcc_one.argtypes = [u64, i64]
         lib.oracle_lcc_one.restype = ctypes.c_double
         lib.oracle_lcc.argtypes = [i64, vp, vp, vp]
@@ -158,6 +160,16 @@ def tc_vertices(g: CSR, vertices) -> np.ndarray:
     lib = _load()
     return np.array([lib.oracle_tc_vertex(_p(g.off), _p(g.adj), int(v), _p(mark)) for v in vertices],
                     dtype=np.uint64)
+
+
+def tc_vertex_pairs(n: int, src, dst, v: int):
+    """(t(v), d(v)) straight from the raw pairs, without a CSR (for sampled checks on graphs
+    whose CSR is too large to build on the host)."""
+    s, d = _arr32(src), _arr32(dst)
+    mark = np.zeros(n, dtype=np.uint8)
+    deg = np.zeros(1, dtype=np.int64)
+    t = _load().oracle_tc_vertex_pairs(len(s), _p(s), _p(d), int(v), _p(mark), _p(deg))
+    return int(t), int(deg[0])
 
 
 def lcc_one(t: int, d: int) -> float:

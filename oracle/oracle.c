@@ -284,6 +284,55 @@ uint64_t oracle_tc_vertex(const int64_t* off, const int32_t* adj, int32_t v, uin
     return c;
 }
 
+/* t(v) and d(v) straight from the raw pairs, for graphs whose CSR is too large to
+ * build here (Sec. II-D's definition over the simple graph of Sec. II-A): one scan
+ * marks adj(v) (loops dropped, repeats marked once), a second gathers every pair
+ * with both ends marked as the key (lower << 32 | higher), and the distinct keys
+ * are the edges {j, k} among the neighbours: t(v) is their number.  mark has n
+ * bytes, all zero on entry and on return; *deg receives d(v). */
+static int cmp_u64(const void* a, const void* b) {
+    const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+uint64_t oracle_tc_vertex_pairs(int64_t m, const int32_t* src, const int32_t* dst, int32_t v, uint8_t* mark,
+                                int64_t* deg) {
+    int64_t d = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t a = src[i], b = dst[i];
+        if (a == b) continue;
+        const int32_t w = a == v ? b : (b == v ? a : -1);
+        if (w >= 0 && !mark[w]) {
+            mark[w] = 1;
+            d++;
+        }
+    }
+    int64_t cap = 1024, cnt = 0;
+    uint64_t* keys = (uint64_t*)malloc((size_t)cap * sizeof(uint64_t));
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t a = src[i], b = dst[i];
+        if (a == b || !mark[a] || !mark[b]) continue;
+        if (cnt == cap) {
+            cap *= 2;
+            keys = (uint64_t*)realloc(keys, (size_t)cap * sizeof(uint64_t));
+        }
+        const uint64_t lo = (uint64_t)(a < b ? a : b), hi = (uint64_t)(a < b ? b : a);
+        keys[cnt++] = lo << 32 | hi;
+    }
+    qsort(keys, (size_t)cnt, sizeof(uint64_t), cmp_u64);
+    uint64_t t = 0;
+    for (int64_t i = 0; i < cnt; ++i)
+        if (i == 0 || keys[i] != keys[i - 1]) t++;
+    free(keys);
+    for (int64_t i = 0; i < m; ++i) {
+        const int32_t a = src[i], b = dst[i];
+        if (a == v) mark[b] = 0;
+        if (b == v) mark[a] = 0;
+    }
+    *deg = d;
+    return t;
+}
+
 /* ------------------------------------------------------------------------- */
 /* LCC (Eq. 2)                                                               */
 /* ------------------------------------------------------------------------- */

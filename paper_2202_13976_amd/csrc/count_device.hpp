@@ -286,8 +286,10 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         uint32_t glast4 = 0;
         auto fetch_tail = [&]() {
             if (gj < nk) {
-                uint64_t off = __builtin_amdgcn_readlane((uint32_t)toff, gj);
-                if constexpr (sizeof(OffT) == 8) off |= (uint64_t)__builtin_amdgcn_readlane((uint32_t)(toff >> 32), gj) << 32;
+                // both halves whatever the offset width: with 4-byte offsets a tail may start at
+                // entry 2^30 or later, whose byte offset needs more than 32 bits
+                const uint64_t off = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)toff, gj) |
+                                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(toff >> 32), gj) << 32);
                 tptr = (const char*)a.adj + off;
                 gend4 = (int32_t)__builtin_amdgcn_readlane(tbytes, gj);
                 gjv = gj;

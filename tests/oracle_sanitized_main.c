@@ -57,6 +57,16 @@ int main(void) {
         }
         for (int64_t v = 0; v < n; ++v) tv[v] = oracle_tc_vertex(off, adj, (int32_t)v, mark);
         bad |= check_equal(tf, tv, n, "vertex at a time vs forward");
+        for (int64_t v = 0; v < n && v < 64; ++v) {
+            int64_t dv = -1;
+            tv[v] = oracle_tc_vertex_pairs(m_in, src, dst, (int32_t)v, mark, &dv);
+            if (dv != off[v + 1] - off[v]) {
+                fprintf(stderr, "vertex from raw pairs: degree %lld of %lld, want %lld\n", (long long)dv, (long long)v,
+                        (long long)(off[v + 1] - off[v]));
+                bad = 1;
+            }
+        }
+        bad |= check_equal(tf, tv, n < 64 ? n : 64, "vertex from raw pairs vs forward");
         oracle_lcc(n, off, tf, lcc);
         uint64_t sum_t = 0, lx = 0;
         for (int64_t v = 0; v < n; ++v) {

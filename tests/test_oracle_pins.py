@@ -312,6 +312,32 @@ def test_vertex_at_a_time_and_ranges():
     assert edges == g.m
 
 
+@settings(max_examples=150, deadline=None)
+@given(st.integers(min_value=1, max_value=30).flatmap(
+    lambda n: st.tuples(st.just(n), st.lists(
+        st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)), max_size=250))))
+def test_vertex_from_raw_pairs_brute_force(case):
+    """t(v) and d(v) straight from raw pairs (repeats, loops, one-direction pairs) equal the
+    independent Python triple enumeration of the simple graph, for every vertex."""
+    n, pairs = case
+    t_ref, _, deg_ref = py_reference(n, pairs)
+    s = np.array([a for a, _ in pairs], dtype=np.int32)
+    d = np.array([b for _, b in pairs], dtype=np.int32)
+    for v in range(n):
+        assert oracle.tc_vertex_pairs(n, s, d, v) == (int(t_ref[v]), int(deg_ref[v])), v
+
+
+def test_vertex_from_raw_pairs_rmat():
+    """The same on an R-MAT graph against the pinned forward count and CSR degrees, on every
+    41st vertex and the hub (the mark array must come back clean between calls)."""
+    n, s, d = synth.rmat_scale(12, 16, seed=21)
+    g = oracle.csr(n, s, d)
+    t = oracle.tc_forward(g)
+    vs = list(range(0, n, 41)) + [int(np.argmax(g.deg))]
+    for v in vs:
+        assert oracle.tc_vertex_pairs(n, s, d, v) == (int(t[v]), int(g.deg[v])), v
+
+
 # --------------------------------------------------------------------------- intersection routines
 
 sorted_lists = st.lists(st.integers(-50, 400), max_size=120).map(lambda x: sorted(set(x)))
