@@ -1070,9 +1070,13 @@ tc_lcc_status build_graph(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
 
 constexpr int kClassWave = 48, kClassList = 49, kClassGlobal = 50, kClassNone = 63;
 
+// bitmap_ok: the vertex's rank bitmap fits a block's table (region_bytes), so the block kernel
+// probes it there whatever the list's length (only lists beyond the block's hash need to know).
+template <typename OffT>
 __global__ void k_classify(const unsigned long long* __restrict__ work, const int32_t* __restrict__ dplus,
-                           int64_t n, int bits, int64_t wave_work_max, int32_t wave_cap, int32_t block_cap,
-                           int32_t list_cap, int group, uint64_t* __restrict__ keys,
+                           const OffT* __restrict__ out_off, const int32_t* __restrict__ adj, int64_t n, int bits,
+                           int64_t wave_work_max, int32_t wave_cap, int32_t block_cap, int32_t list_cap,
+                           uint32_t region_bytes, int group, uint64_t* __restrict__ keys,
                            unsigned long long* __restrict__ counts) {
     __shared__ unsigned int c[64];
     for (int i = threadIdx.x; i < 64; i += blockDim.x) c[i] = 0;
@@ -1080,12 +1084,17 @@ __global__ void k_classify(const unsigned long long* __restrict__ work, const in
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const unsigned long long w = work[v];
         const int32_t dp = dplus[v];
+        bool bitmap_ok = false;
+        if (region_bytes > 0 && dp > block_cap) {
+            const uint32_t span = (uint32_t)(adj[out_off[v + 1] - 1] - (int32_t)v);
+            bitmap_ok = bitmap_bytes((span + 31u) >> 5, dp) <= region_bytes;
+        }
         int cls;
         if (w == 0) {
             cls = kClassNone;
-        } else if (dp > list_cap) {
+        } else if (dp > list_cap && !bitmap_ok) {
             cls = kClassGlobal;
-        } else if (dp > block_cap) {
+        } else if (dp > block_cap && !bitmap_ok) {
             cls = kClassList;
         } else if (dp <= wave_cap && (group == 1 || (group == 0 && (int64_t)w <= wave_work_max))) {
             cls = kClassWave;
@@ -1146,9 +1155,17 @@ tc_lcc_status build_schedule(tc_lcc_graph g, const tc_lcc_tuning& tn, hipStream_
     TCL_HIP(fill<unsigned long long>(counts, 64, 0ull, st));
     TCL_HIP(fill<unsigned int>(sort_err, 64, 0u, st));
     const int group = tn.group;
-    k_classify<<<grid_for(n, kB, 4096), kB, 0, st>>>((const unsigned long long*)d.work, d.dplus, d.n, d.bits,
-                                                     tn.wave_work_max, wave_cap, block_cap, list_cap, group, ka,
-                                                     counts);
+    // the bitmap is taken wherever it fits with the automatic probe (not with hash, sorted or
+    // merge), so there a long list whose bitmap fits the block's table stays in the block bins
+    const uint32_t bm_region = probe == TC_LCC_PROBE_AUTO ? (uint32_t)slots * 8u : 0u;
+    if (d.compact || d.off_bytes == 8)
+        k_classify<int64_t><<<grid_for(n, kB, 4096), kB, 0, st>>>(
+            (const unsigned long long*)d.work, d.dplus, (const int64_t*)d.out_off, d.adj, d.n, d.bits,
+            tn.wave_work_max, wave_cap, block_cap, list_cap, bm_region, group, ka, counts);
+    else
+        k_classify<int32_t><<<grid_for(n, kB, 4096), kB, 0, st>>>(
+            (const unsigned long long*)d.work, d.dplus, (const int32_t*)d.out_off, d.adj, d.n, d.bits,
+            tn.wave_work_max, wave_cap, block_cap, list_cap, bm_region, group, ka, counts);
     TCL_HIP(hipGetLastError());
     // keys are written in vertex order: a stable sort on the 6 class bits keeps vertices
     // ascending within a class

@@ -494,12 +494,6 @@ __device__ void walk_tails_hybrid(const CountArgs<OffT>& a, int32_t v, const Tab
     }
 }
 
-// Bytes of the bitmap layout for `words` bitmap words (plus the guard word), dv counters and
-// one spare word per lane.
-__host__ __device__ __forceinline__ uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
-    return 8u * (words + 1u) + 4u * (uint32_t)dv + 4u * kWave;
-}
-
 // One vertex v, processed by a group of NWAVES waves (gtid = thread index in the group,
 // wig = wave index in the group) with an LDS region of region_bytes.  The probe method is
 // chosen per vertex: the rank bitmap when it fits (AUTO or BITMAP), else the hash; or the

@@ -48,6 +48,14 @@ __host__ __device__ inline int32_t hash_table_slots(int32_t dv) {
 }
 __host__ __device__ inline int32_t hash_capacity(int32_t T) { return T / 2; }
 
+// LDS bytes of the rank bitmap of a list of dv entries spanning `words` 32-rank words: the words
+// with their first indices (plus a zero guard word), dv counters and one spare word per lane.
+// The count takes the bitmap for a vertex wherever this fits its region, and the schedule keeps
+// a block vertex whose list exceeds the hash in the block bins when it fits the block's table.
+__host__ __device__ inline uint32_t bitmap_bytes(uint32_t words, int32_t dv) {
+    return 8u * (words + 1u) + 4u * (uint32_t)dv + 4u * kWave;
+}
+
 // ------------------------------------------------------------------ device memory pool
 // Caching allocator per context.  Blocks are rounded to size classes and kept on
 // free lists after release; the budget covers blocks in use plus cached blocks.

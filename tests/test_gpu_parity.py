@@ -137,10 +137,10 @@ def test_rmat_s23_full(ctx):
 def test_dense_core_list_and_global_paths(ctx):
     """A dense core that is not a clique (13 parts of 200, 5 % of the cross pairs dropped) with
     an R-MAT periphery: |N+(v)| passes 2048 at the lowest-ranked core vertices and most
-    candidates of a core list miss.  The default probe sends those lists to the block table
-    as a sorted list, the hash-only probe to the global-memory path (the miss branch of both
-    runs); the sorted and hybrid probes take them in LDS.  Every vertex against the oracle's
-    digests."""
+    candidates of a core list miss.  The default probe keeps those lists in the block table as
+    a rank bitmap (their ranks lie close together, so the bitmap fits), the hash-only probe sends
+    them to the global-memory path (the miss branch runs); the sorted and hybrid probes take
+    them in LDS.  Every vertex against the oracle's digests."""
     name = "dense_core_13x200_drop5_p11_seed61"
     n, s, d = synth.dense_core(13, 200, 0.05, 11, 61)
     probe0 = ctx.tuning().probe
@@ -162,11 +162,13 @@ def test_dense_core_list_and_global_paths(ctx):
         ctx.set_tuning(probe=probe0)
 
 
-def test_multipartite_beyond_every_table(ctx):
+@pytest.mark.parametrize("probe", [pkg.PROBE_AUTO, pkg.PROBE_HASH])
+def test_multipartite_beyond_every_table(ctx, probe):
     """Complete 50-partite graph with parts of 100: all degrees equal, so ranks follow ids, the
     first part has no in-edges, and the first vertex of every later part has |N+(v)| of up to
-    n - 2 * 100 = 4800, beyond the LDS table even as a sorted list: the default probe searches
-    those lists in HBM, and a candidate in the vertex's own part misses.  Closed form
+    n - 2 * 100 = 4800, beyond the LDS table even as a sorted list.  The default probe takes
+    those lists as rank bitmaps in the block table (4800 ranks span 150 words); the hash-only
+    probe searches them in HBM, where a candidate in the vertex's own part misses.  Closed form
     t = C(4900, 2) - 49 C(100, 2), LCC = 2t/(d(d-1)) (pinned in the oracle tests), and the
     oracle on sampled vertices."""
     k, size = 50, 100
@@ -174,14 +176,19 @@ def test_multipartite_beyond_every_table(ctx):
     iu, ju = np.triu_indices(nn, 1)
     keep = (iu // size) != (ju // size)
     s, d = iu[keep].astype(np.int32), ju[keep].astype(np.int32)
-    say(f"[gpu] complete {k}-partite, parts of {size}")
-    g = ctx.build_csr(nn, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+    say(f"[gpu] complete {k}-partite, parts of {size}, probe {probe}")
+    probe0 = ctx.tuning().probe
+    ctx.set_tuning(probe=probe)
     try:
-        assert g.info().global_vertices > 0
-        tri, lcc = g.run()
-        torch.cuda.synchronize()
+        g = ctx.build_csr(nn, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
+        try:
+            assert (g.info().global_vertices > 0) == (probe == pkg.PROBE_HASH)
+            tri, lcc = g.run()
+            torch.cuda.synchronize()
+        finally:
+            g.free()
     finally:
-        g.free()
+        ctx.set_tuning(probe=probe0)
     t = tri.cpu().numpy().astype(np.uint64)
     deg = (k - 1) * size
     want = math.comb(deg, 2) - (k - 1) * math.comb(size, 2)
@@ -312,8 +319,8 @@ def clique(n):
 
 def test_large_clique_global_path(ctx):
     """K_2800: |N+(v)| reaches 2799, beyond the largest hash table (2048 keys at load 1/2):
-    by default such vertices take the block table as a sorted list; with the hash-only probe
-    they take the global-memory path.  Reference: the closed form for K_n (t = C(n-1, 2),
+    by default such vertices keep the block table as a rank bitmap (their ranks are
+    consecutive); with the hash-only probe they take the global-memory path.  Reference: the closed form for K_n (t = C(n-1, 2),
     LCC = 1), which the oracle's own pins establish; running the oracle on 3.9 M edges would be
     slow."""
     n = 2800
@@ -335,14 +342,20 @@ def test_large_clique_global_path(ctx):
 
 
 def test_clique_beyond_every_table(ctx):
-    """K_4500: |N+(v)| reaches 4499, beyond the LDS table even as a sorted list (4096 keys), so
-    the default probe sends ranks 1..402 to the global-memory path (rank 0 has no in-edge, so
-    no work).  Reference: the closed form for K_n."""
-    n = 4500
+    """K_8200: |N+(v)| reaches 8199, beyond the LDS table even as a sorted list (4096 keys), and
+    the longest lists' rank bitmaps (their words, first indices, counters and spare words) exceed
+    the block's 32 KiB too, so the default probe sends those ranks to the global-memory path
+    (rank 0 has no in-edge, so no work); the shorter lists beyond the hash take the bitmap.
+    Reference: the closed form for K_n."""
+    n = 8200
     say(f"[gpu] K{n} (global path under the default probe)")
     s, d = (x.astype(np.int32) for x in np.triu_indices(n, 1))
     g = ctx.build_csr(n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda(), offset_bytes=8)
-    assert g.info().global_vertices == n - 2 - 4096
+    # rank r holds N+ = {r + 1 .. n - 1}: dv = n - 1 - r entries over a span of dv ranks
+    dv = n - 1 - np.arange(1, n - 1)
+    bitmap = 8 * (((dv + 31) >> 5) + 1) + 4 * dv + 4 * 64
+    want_global = int(np.count_nonzero((dv > 4096) & (bitmap > 4096 * 8)))
+    assert want_global > 0 and g.info().global_vertices == want_global
     tri, lcc = g.run()
     torch.cuda.synchronize()
     assert bool((tri == (n - 1) * (n - 2) // 2).all()) and bool((lcc == 1.0).all())

@@ -175,21 +175,26 @@ def test_streamed_dense_core_list_and_global_paths(ctx):
         ctx.set_tuning(probe=probe0)
 
 
-def test_streamed_multipartite_beyond_every_table(ctx):
+@pytest.mark.parametrize("probe", [pkg.PROBE_AUTO, pkg.PROBE_HASH])
+def test_streamed_multipartite_beyond_every_table(ctx, probe):
     """Complete 50-partite graph with parts of 100: oriented lists of up to 4800 entries, beyond
-    the LDS table, searched in HBM; closed form t = C(4900, 2) - 49 C(100, 2) (pinned in the
+    the LDS table's hash and sorted list: rank bitmaps in the block table by default, searched in
+    HBM with the hash-only probe; closed form t = C(4900, 2) - 49 C(100, 2) (pinned in the
     oracle tests) for every vertex."""
     k, size = 50, 100
     nn = k * size
     iu, ju = np.triu_indices(nn, 1)
     keep = (iu // size) != (ju // size)
     s, d = iu[keep].astype(np.int32), ju[keep].astype(np.int32)
-    say(f"[gpu] streamed complete {k}-partite, parts of {size}, 4 partitions")
+    say(f"[gpu] streamed complete {k}-partite, parts of {size}, 4 partitions, probe {probe}")
     src = synth.DevicePairs(dev(s), dev(d))
-    g = ctx.build_streamed(nn, len(s), src.gen, chunk_pairs=1 << 21, partition_pairs=len(s) // 4)
+    probe0 = ctx.tuning().probe
+    ctx.set_tuning(probe=probe)
+    g = None
     try:
+        g = ctx.build_streamed(nn, len(s), src.gen, chunk_pairs=1 << 21, partition_pairs=len(s) // 4)
         info = g.info()
-        assert info.max_out_degree > 4096 and info.global_vertices > 0
+        assert info.max_out_degree > 4096 and (info.global_vertices > 0) == (probe == pkg.PROBE_HASH)
         tri, lcc = g.run()
         torch.cuda.synchronize()
         dg = (k - 1) * size
@@ -198,7 +203,9 @@ def test_streamed_multipartite_beyond_every_table(ctx):
         want = np.float64(2 * t_each) / np.float64(dg * (dg - 1))
         assert np.all(lcc.cpu().numpy() == want)
     finally:
-        g.free()
+        if g is not None:
+            g.free()
+        ctx.set_tuning(probe=probe0)
 
 
 # ------------------------------------------------------------------ errors and other paths
