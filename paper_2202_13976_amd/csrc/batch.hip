@@ -283,20 +283,14 @@ __global__ __launch_bounds__(kBatchThreads, 7) void k_batch_light(const BatchGra
 __global__ __launch_bounds__(256) void k_batch_epilogue(const BatchGraph* __restrict__ gs, const BatchHeader* h) {
     const int count = h->count;
     const int64_t chunks = h->chunks;
-    const int lane = lane_id();
     for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        // the last graph with chunk_base <= c, found by each wave with 64 graphs tested per round
-        // (two rounds for 4096 graphs) instead of a one-lane binary search of twelve loads
-        int lo = 0, hi = count;
-        while (hi - lo > 1) {
-            const int step = (hi - lo + kWave - 1) / kWave;
-            const int gi = lo + lane * step;
-            const bool pass = gi < hi && gs[gi].chunk_base <= c;
-            const int k = (int)__popcll(__builtin_amdgcn_ballot_w64(pass));
-            lo += (k - 1) * step;
-            hi = min(hi, lo + step);
+        int ga = 0, gb = count - 1;  // last graph with chunk_base <= c
+        while (ga < gb) {
+            const int mid = (ga + gb + 1) >> 1;
+            if (gs[mid].chunk_base <= c) ga = mid;
+            else gb = mid - 1;
         }
-        const int g = __builtin_amdgcn_readfirstlane(lo);
+        const int g = __builtin_amdgcn_readfirstlane(ga);
         const BatchGraph& G = gs[g];
         const int64_t r0 = (c - G.chunk_base) * kEpiChunk;
         const int64_t r1 = min(r0 + (int64_t)kEpiChunk, G.n);
