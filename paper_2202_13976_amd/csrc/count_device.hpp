@@ -304,7 +304,7 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         // next tail
         auto advance = [&]() {
             gbase4 += kWave * 4;
-            if (gbase4 >= gend4) {
+            if (__builtin_expect(gbase4 >= gend4, 0)) {
                 gbase4 = 0;
                 gj += 1;
                 fetch_tail();
@@ -328,18 +328,11 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         int32_t xs[kRing];
 #pragma unroll
         for (int q = 0; q < kRing; ++q) xs[q] = gen(js[q], lims[q]);
-        int cur_j = 0;       // tail whose hits accumulate in cur_c (windows come in tail order)
-        uint32_t cur_c = 0;  // wave-uniform
-        // a tail's count is written to its owner lane once, when the next tail starts (every
-        // tail has at least one window)
+        // a window's hits go to the lane that owns its tail (a compare and a select on the
+        // vector side; no tail-switch branch)
         auto account = [&](int j, unsigned long long H) {
-            if (j != cur_j) {
-                // lane cur_j of `mine` := cur_c (a register write, no memory access)
-                asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(__builtin_amdgcn_readfirstlane(cur_c)), "{m0}"(cur_j));
-                cur_j = j;
-                cur_c = 0;
-            }
-            cur_c += (uint32_t)__popcll(H);
+            const uint32_t c = (uint32_t)__popcll(H);
+            mine += lane == j ? c : 0u;
         };
         while (js[0] >= 0) {
 #pragma unroll
@@ -391,7 +384,6 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
                 }
             }
         }
-        asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(__builtin_amdgcn_readfirstlane(cur_c)), "{m0}"(cur_j));
         local += mine;
         if (ok && mine) gadd(a.t + u, (unsigned long long)mine);
     }
