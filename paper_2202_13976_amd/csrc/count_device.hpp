@@ -272,9 +272,10 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         const int nk = (int)__builtin_amdgcn_readfirstlane(
             rest <= 0 ? 0 : (int)min((OffT)kWave, (rest + NWAVES - 1) / NWAVES));
         uint32_t mine = 0;  // hits of the tail this lane owns (tail index == lane)
-        // this lane's tail as a byte offset into adj and a byte length, formed once per chunk
-        // (the tail pointer is adj plus the offset, so loads stay in the global address space)
-        const uint64_t toff = (uint64_t)st * 4u;
+        // this lane's tail as an address and a byte length, formed once per chunk, so that a
+        // tail switch only reads them out of the owner lane (the loads cast the address to the
+        // global address space)
+        const uint64_t taddr = (uint64_t)(uintptr_t)a.adj + (uint64_t)st * 4u;
         const uint32_t tbytes = (uint32_t)len * 4u;
 
         // generator (wave-uniform): tail gj (gjv = gj while gj < nk, else -1), next window at
@@ -286,11 +287,9 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         uint32_t glast4 = 0;
         auto fetch_tail = [&]() {
             if (gj < nk) {
-                // both halves whatever the offset width: with 4-byte offsets a tail may start at
-                // entry 2^30 or later, whose byte offset needs more than 32 bits
-                const uint64_t off = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)toff, gj) |
-                                     ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(toff >> 32), gj) << 32);
-                tptr = (const char*)a.adj + off;
+                tptr = (const char*)(uintptr_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)taddr, gj) |
+                                                 ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(taddr >> 32), gj)
+                                                  << 32));
                 gend4 = (int32_t)__builtin_amdgcn_readlane(tbytes, gj);
                 gjv = gj;
             } else {

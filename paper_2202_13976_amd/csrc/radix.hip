@@ -21,11 +21,11 @@
 
 namespace tcl {
 
-constexpr int kSortThreads = 512;
+constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kSortItems = 32;                        // keys per thread
+constexpr int kSortItems = 16;                        // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;  // 16384 keys per tile (128 KiB staged in LDS)
-constexpr int kWaveSpan = kSortTile / kSortWaves;     // 2048 keys per wave
+constexpr int kWaveSpan = kSortTile / kSortWaves;     // 1024 keys per wave
 constexpr uint64_t kAggregate = 1ull << 62;  // status: the tile's own count is published
 constexpr uint64_t kInclusive = 2ull << 62;  // status: the running total through the tile
 constexpr uint64_t kValueMask = (1ull << 62) - 1;
@@ -173,12 +173,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(const K* __restrict
         gstart[d] = base[d] + (uint32_t)excl;
     }
     __syncthreads();
+    // per wave and digit: the staged slot of the wave's first key of that digit; per digit: its
+    // output position less its staged position (modulo 2^32), so that each key reads one word
+    for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] += tstart[i & 255];
+    __syncthreads();
+    if (threadIdx.x < 256) gstart[threadIdx.x] -= tstart[threadIdx.x];
 #pragma unroll
     for (int c = 0; c < kSortItems; ++c) {
         const size_t idx = wbeg + (size_t)c * kWave + lane;
         if (idx < n) {
             const uint32_t d = (uint32_t)(k[c] >> shift) & 255u;
-            stage[tstart[d] + wcnt[w][d] + r[c]] = k[c];
+            stage[wcnt[w][d] + r[c]] = k[c];
         }
     }
     __syncthreads();
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(const K* __restrict
     for (int i = threadIdx.x; i < tile_n; i += kSortThreads) {
         const K key = stage[i];
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
-        out[(size_t)gstart[d] + (uint32_t)i - tstart[d]] = key;
+        out[(size_t)(uint32_t)(gstart[d] + (uint32_t)i)] = key;  // n < 2^32
     }
 }
 
