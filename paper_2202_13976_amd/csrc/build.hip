@@ -465,6 +465,18 @@ __global__ void k_max_i32(const int32_t* __restrict__ x, int64_t n, int* __restr
     if (lane_id() == 0) atomicMax(out, mx);
 }
 
+// One bit per vertex r: N+(r) is nonempty (bit r % 32 of word r / 32).  A megabyte at 2^23
+// vertices, which the L2 holds while the edges look their targets up in it.
+__global__ void k_nonempty_bits(const int32_t* __restrict__ dplus, int64_t n, uint32_t* __restrict__ bits) {
+    GRID_STRIDE(r, n) {
+        const unsigned long long b = __builtin_amdgcn_ballot_w64(dplus[r] > 0);
+        const int lane = lane_id();
+        // lanes hold consecutive r and a wave starts at a multiple of 64
+        if (lane == 0) bits[r >> 5] = (uint32_t)b;
+        else if (lane == 32) bits[r >> 5] = (uint32_t)(b >> 32);
+    }
+}
+
 // What the reverse lists need of oriented edge i = (u -> v), besides its tail start i + 1:
 // u and the tail length.
 struct EdgePay {
@@ -489,7 +501,7 @@ struct InWord {
 // above every vertex, so it sorts after all in-edges that are kept.
 template <typename OffT>
 __global__ __launch_bounds__(kB) void k_edge_emit(const uint64_t* __restrict__ ok, size_t m, int bits, InWord iw,
-                                                  const OffT* __restrict__ out_off, const int32_t* __restrict__ dplus,
+                                                  const OffT* __restrict__ out_off, const uint32_t* __restrict__ nonempty,
                                                   int32_t* __restrict__ adj, uint64_t* __restrict__ words,
                                                   EdgePay* __restrict__ pay, uint32_t* __restrict__ hist) {
     __shared__ DigitCounts dc;
@@ -501,7 +513,7 @@ __global__ __launch_bounds__(kB) void k_edge_emit(const uint64_t* __restrict__ o
         const int64_t u = (int64_t)(x >> bits), v = (int64_t)(x & mask);
         adj[i] = (int32_t)v;
         const int64_t len = (int64_t)out_off[u + 1] - (int64_t)i - 1;
-        const bool kept = len > 0 && dplus[v] > 0;
+        const bool kept = len > 0 && ((nonempty[v >> 5] >> (v & 31)) & 1u);
         const uint64_t key = kept ? (uint64_t)v : (1ull << bits);
         uint64_t w;
         if (iw.packed) {
@@ -945,8 +957,13 @@ tc_lcc_status build_typed(tc_lcc_ctx ctx, int64_t n, int64_t m_in, const int32_t
         TCL_TRY(tmp.get(std::max<size_t>(m, 1), &pay));
     }
     if (m > 0) {
+        // the kept test looks targets up in a bitmap of nonempty lists that the L2 holds
+        uint32_t* nonempty;
+        TCL_TRY(tmp.get((N + 63) / 32, &nonempty));
+        k_nonempty_bits<<<grid_for(N, kB, 4096), kB, 0, st>>>(d.dplus, n, nonempty);
+        TCL_HIP(hipGetLastError());
         TCL_HIP(radix_counts_clear(sort_scratch, st));
-        k_edge_emit<OffT><<<grid_for(m, kB, 1024), kB, 0, st>>>(osorted, m, bits, iw, out_off, d.dplus, d.adj, wa,
+        k_edge_emit<OffT><<<grid_for(m, kB, 1024), kB, 0, st>>>(osorted, m, bits, iw, out_off, nonempty, d.adj, wa,
                                                                 pay, radix_counts(sort_scratch));
         TCL_HIP(hipGetLastError());
         TCL_HIP(radix_sort_u64(wa, wb, m, iw.vshift, bits + 1, sort_scratch, sort_err, st, &ws, true));
