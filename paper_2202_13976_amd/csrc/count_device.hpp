@@ -327,11 +327,15 @@ __device__ __forceinline__ void walk_tails(const CountArgs<OffT>& a, const InEdg
         int32_t xs[kRing];
 #pragma unroll
         for (int q = 0; q < kRing; ++q) xs[q] = gen(js[q], lims[q]);
-        // a window's hits go to the lane that owns its tail (a compare and a select on the
-        // vector side; no tail-switch branch)
+        // a window's hits go to the lane that owns its tail: one vector add with only that lane
+        // in the exec mask (saved and restored around it), no tail-switch branch
         auto account = [&](int j, unsigned long long H) {
             const uint32_t c = (uint32_t)__popcll(H);
-            mine += lane == j ? c : 0u;
+            const unsigned long long m = 1ull << (j & 63);
+            unsigned long long saved;
+            asm volatile("s_and_saveexec_b64 %1, %2\n\tv_add_u32 %0, %3, %0\n\ts_mov_b64 exec, %1"
+                         : "+v"(mine), "=&s"(saved)
+                         : "s"(m), "s"(c));
         };
         while (js[0] >= 0) {
 #pragma unroll
